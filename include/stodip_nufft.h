@@ -1,0 +1,200 @@
+/*
+ * stodip_nufft.h - C ABI of the MI355X multicoil subspace NUFFT library.
+ *
+ * The library evaluates the forward operator of MRF reconstruction and its
+ * adjoint (StoDIP, arXiv 2408.02367, Sec. 2 and Eq. 1-3):
+ *
+ *   A_c : x (K subspace images) -> coil c k-space
+ *   y_b(j) = sum_k V[t_j, k] * NUFFT2(S_{c_b} * x_k)(k_j)
+ *   xbar_k = sum_b conj(S_{c_b}) * NUFFT1(conj(V[t_j, k]) * r_b(j))
+ *
+ * where the NUFFT is a Kaiser-Bessel gridding NUFFT (width W, oversampling
+ * sigma) and t_j is the timeframe of sample j.  The DC loss of Eq. 2-3 and
+ * its gradient are sdn_mrf_dc_grad.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Every call returns sdn_status (0 = SDN_OK, negative = error); no C++
+ *   exception crosses the ABI.  sdn_last_error() gives a message for the
+ *   last non-OK status of the calling thread.
+ * - "dev" pointers are HIP device pointers owned by the caller; the library
+ *   never frees or retains them beyond the call.  Complex arrays are
+ *   complex64 (interleaved float re, im) and contiguous.
+ * - Images are [..][Nz][Ny][Nx] with x fastest; mode n_d sits at array
+ *   index n_d + floor(N_d/2) (centred).  Trajectories are [M][3] float32
+ *   radians per voxel with columns (kx, ky, kz) paired with (x, y, z).
+ * - The type-2 transform uses exp(-i k.n), the type-1 exp(+i k.n); neither
+ *   is normalised, so the adjoint is the exact adjoint.
+ * - k-space arrays are in the caller's point order.
+ * - `stream` is a hipStream_t (NULL = the legacy default stream).  Work is
+ *   enqueued asynchronously; only sdn_plan_create synchronises.
+ * - One call in flight per plan at a time (the plan owns its workspace).
+ */
+#ifndef STODIP_NUFFT_H
+#define STODIP_NUFFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__)
+#define SDN_API __attribute__((visibility("default")))
+#else
+#define SDN_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sdn_plan_s *sdn_plan;
+
+typedef enum {
+  SDN_OK = 0,
+  SDN_E_INVALID = -1,     /* bad argument: null pointer, bad size or shape */
+  SDN_E_RANGE = -2,       /* non-finite coordinate, index out of range     */
+  SDN_E_NOMEM = -3,       /* device allocation failed or budget too small  */
+  SDN_E_UNSUPPORTED = -4, /* valid request the library does not implement  */
+  SDN_E_HIP = -5,         /* a HIP runtime call or kernel launch failed    */
+  SDN_E_STATE = -6        /* plan in the wrong state (e.g. destroyed)      */
+} sdn_status;
+
+/* Plan options.  Fill with sdn_default_opts() and override. */
+typedef struct {
+  int W;                   /* kernel width in fine-grid cells: 4, 6 or 8 (default 6) */
+  double sigma;            /* oversampling ratio, 1.25 <= sigma <= 4 (default 2.0)   */
+  int tile;                /* bin / tile edge in fine cells; 0 = library choice       */
+  int max_points_per_item; /* cap on points per spreading work item; 0 = library     */
+  size_t workspace_budget; /* bytes of fine-grid workspace; 0 = unlimited.  Calls
+                              whose coil minibatch does not fit run coil-chunked.   */
+} sdn_opts;
+
+/* Plan facts, for callers and tests. */
+typedef struct {
+  int64_t shape[3];        /* (Nz, Ny, Nx) image shape                               */
+  int64_t fine[3];         /* (nfz, nfy, nfx) oversampled grid                       */
+  int64_t M;               /* points                                                */
+  int32_t T;               /* frames (rows of V)                                    */
+  int W;
+  double sigma, beta;      /* Kaiser-Bessel shape parameter                          */
+  int64_t tile[3];         /* (bz, by, bx)                                          */
+  int64_t nbins;           /* tiles of the fine grid                                */
+  int64_t nwork;           /* spreading work items (hot tiles split)                 */
+  int64_t max_bin;         /* points in the most populated tile                      */
+  int ncoef;               /* coefficients per piece of the kernel polynomial        */
+} sdn_plan_info;
+
+/* Library defaults: W = 6, sigma = 2, automatic tiles, no budget. */
+SDN_API void sdn_default_opts(sdn_opts *opts);
+
+/*
+ * Build a plan for one trajectory and image shape (the "plan(traj, N, sigma,
+ * W)" call; the trajectory is fixed across all DC steps of a scan, Sec. 3).
+ *
+ *   shape           host int64[3] = (Nz, Ny, Nx), each >= 1
+ *   traj            dev float32 [M][3] radians per voxel; any finite value is
+ *                   folded modulo 2 pi; |k| > 2^20 or NaN/Inf -> SDN_E_RANGE
+ *   M               points, >= 0 (M = 0 is a valid, empty plan)
+ *   frame_of_point  dev int32 [M] timeframe of each point in [0, T), or NULL
+ *                   (all points in frame 0; T may then be 0 or 1)
+ *   opts            NULL = defaults
+ * The plan sorts the points into fine-grid tiles on the device and keeps
+ * its own copy of everything it needs; the caller may free traj and
+ * frame_of_point afterwards.  Synchronises `stream`.
+ */
+SDN_API sdn_status sdn_plan_create(sdn_plan *out, const int64_t shape[3], const float *traj,
+                           int64_t M, const int32_t *frame_of_point, int32_t T,
+                           const sdn_opts *opts, void *stream);
+
+/* Free every device and host resource of the plan.  NULL is a no-op. */
+SDN_API sdn_status sdn_plan_destroy(sdn_plan plan);
+
+SDN_API sdn_status sdn_plan_get_info(sdn_plan plan, sdn_plan_info *info);
+
+/*
+ * Plain type-2 NUFFT of `batch` images (uniform -> nonuniform):
+ *   ksp[b][j] = sum_n img[b][n] exp(-i k_j . n)
+ *   img  dev complex64 [batch][Nz][Ny][Nx];  ksp dev complex64 [batch][M]
+ */
+SDN_API sdn_status sdn_forward(sdn_plan plan, const void *img, void *ksp, int batch, void *stream);
+
+/*
+ * Plain type-1 NUFFT (nonuniform -> uniform), the adjoint of sdn_forward:
+ *   img[b][n] = sum_j ksp[b][j] exp(+i k_j . n)
+ */
+SDN_API sdn_status sdn_adjoint(sdn_plan plan, const void *ksp, void *img, int batch, void *stream);
+
+/*
+ * MRF subspace forward operator for a coil minibatch (Sec. 2; Eq. 3's A_c;
+ * Algorithm 1's forward step), all B*K (coil, channel) pairs batched:
+ *   y[b][j] = sum_k V[t_j][k] * NUFFT2(smaps[coil_idx[b]] * x[k])(k_j)
+ *
+ *   x        dev complex64 [K][Nz][Ny][Nx], 1 <= K <= 8
+ *   smaps    dev complex64 [C][Nz][Ny][Nx] coil sensitivities
+ *   coil_idx host int32 [B], each in [0, C), 1 <= B <= 64
+ *   V        dev complex64 [T][K] temporal subspace basis (row t_j is used)
+ *   y        dev complex64 [B][M] (overwritten)
+ */
+SDN_API sdn_status sdn_mrf_forward(sdn_plan plan, const void *x, int K, const void *smaps, int C,
+                           const int32_t *coil_idx, int B, const void *V, void *y,
+                           void *stream);
+
+/*
+ * Adjoint of sdn_mrf_forward (the backward of Algorithm 1's loss.backward()):
+ *   x_out[k] (+)= sum_b conj(smaps[coil_idx[b]]) * NUFFT1(conj(V[t_j][k]) * y[b][j])
+ *   y      dev complex64 [B][M];  x_out dev complex64 [K][Nz][Ny][Nx]
+ *   accumulate = 0 overwrites x_out, 1 adds to it.
+ */
+SDN_API sdn_status sdn_mrf_adjoint(sdn_plan plan, const void *y, int K, const void *smaps, int C,
+                           const int32_t *coil_idx, int B, const void *V, void *x_out,
+                           int accumulate, void *stream);
+
+/*
+ * Data-consistency loss and gradient of Eq. 2-3 for a coil minibatch, fused:
+ *   loss = sum_b sum_j w_j |(A x)_b(j) - d[b][j]|^2
+ *   grad = 2 A^H (w (A x - d))          (PyTorch's complex gradient convention)
+ *   d     dev complex64 [B][M] measured k-space of the minibatch coils
+ *   w     dev float32 [M] density-compensation weights, or NULL (w = 1)
+ *   loss  dev double [1] (overwritten)
+ *   grad  dev complex64 [K][Nz][Ny][Nx] (overwritten)
+ */
+SDN_API sdn_status sdn_mrf_dc_grad(sdn_plan plan, const void *x, int K, const void *smaps, int C,
+                           const int32_t *coil_idx, int B, const void *V, const void *d,
+                           const float *w, double *loss, void *grad, void *stream);
+
+/*
+ * The same operators evaluated the plain way, one (coil, channel) pair per
+ * NUFFT with separate subspace-mix kernels: the per-coil/per-channel
+ * baseline the batched calls are measured against.  Arguments as above.
+ */
+SDN_API sdn_status sdn_mrf_forward_plain(sdn_plan plan, const void *x, int K, const void *smaps,
+                                 int C, const int32_t *coil_idx, int B, const void *V,
+                                 void *y, void *stream);
+SDN_API sdn_status sdn_mrf_adjoint_plain(sdn_plan plan, const void *y, int K, const void *smaps,
+                                 int C, const int32_t *coil_idx, int B, const void *V,
+                                 void *x_out, int accumulate, void *stream);
+
+/* Device workspace (bytes) a call with B coils and K channels would hold. */
+SDN_API sdn_status sdn_workspace_size(sdn_plan plan, int B, int K, size_t *bytes);
+
+/* Release the plan's cached workspace (it is re-allocated on demand). */
+SDN_API sdn_status sdn_release_workspace(sdn_plan plan);
+
+/*
+ * Host-only view of the kernel tables a plan would use (no device work):
+ * the shape parameter beta, the fine length of an axis of N modes, the
+ * piecewise-polynomial kernel (coef[i * 16 + d] is the z^d coefficient of
+ * node i, z = 2t - 1, normalised so the kernel peak is 1) and the
+ * deapodisation factors 1 / phi_hat(n / nf) on the same normalisation for
+ * array index n + floor(N/2).  coef: host float[8 * 16]; deapod_inv: host
+ * float[N] or NULL.  For tests and diagnostics.
+ */
+SDN_API sdn_status sdn_kernel_tables(int W, double sigma, int64_t N, double *beta, int *nf,
+                                     int *ncoef, float *coef, float *deapod_inv);
+
+/* Message for the calling thread's last non-OK status ("" if none). */
+SDN_API const char *sdn_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* STODIP_NUFFT_H */

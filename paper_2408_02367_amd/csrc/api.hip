@@ -1,0 +1,383 @@
+// Entry points of the C ABI: plain type-2 / type-1 NUFFTs, the batched MRF
+// subspace operator A_c and its adjoint, the fused DC gradient, and the
+// plain per-coil/per-channel form of the same operators.
+//
+// Batched calls put all B*K (coil, channel) pairs of the minibatch through
+// each stage in one launch: fused x pass, y pass, z pass, interpolation
+// with the subspace mix (forward) and spread with the conjugate mix, two
+// inverse passes and the fused x pass that sums over coils (adjoint).  The
+// forward's fine grids are never kept for the adjoint: A is linear, so its
+// adjoint needs none of them, and the same workspace serves both.
+#include <algorithm>
+#include <string>
+
+#include "sdn_internal.h"
+
+using namespace sdn;
+
+namespace {
+
+sdn_status check_plan(sdn_plan p, const char *fn) {
+  if (!p || p->magic != kPlanMagic)
+    return fail(SDN_E_STATE, std::string(fn) + ": not a live plan");
+  return SDN_OK;
+}
+
+size_t fine_cells(const sdn_plan_s &p) {
+  return (size_t)p.ax[0].nf * p.ax[1].nf * p.ax[2].nf;
+}
+
+size_t image_voxels(const sdn_plan_s &p) {
+  return (size_t)p.ax[0].N * p.ax[1].N * p.ax[2].N;
+}
+
+sdn_status ensure_grid(sdn_plan_s *p, size_t elems) {
+  elems += elems & 1;   // whole float4s for the fill kernel
+  if (p->grid_cap >= elems) return SDN_OK;
+  if (p->grid) (void)hipFree(p->grid);
+  p->grid = nullptr;
+  p->grid_cap = 0;
+  sdn_status s = hip_check(hipMalloc((void **)&p->grid, elems * sizeof(float2)),
+                           "fine-grid workspace");
+  if (s == SDN_OK) p->grid_cap = elems;
+  return s;
+}
+
+sdn_status ensure_kbuf(sdn_plan_s *p, size_t elems) {
+  if (p->kbuf_cap >= elems) return SDN_OK;
+  if (p->kbuf) (void)hipFree(p->kbuf);
+  p->kbuf = nullptr;
+  p->kbuf_cap = 0;
+  sdn_status s = hip_check(hipMalloc((void **)&p->kbuf, elems * sizeof(float2)),
+                           "k-space workspace");
+  if (s == SDN_OK) p->kbuf_cap = elems;
+  return s;
+}
+
+// Channels of P-channel grids that fit the workspace budget at once.
+sdn_status channels_per_pass(const sdn_plan_s &p, int unit, int units, int *per,
+                             const char *fn) {
+  const size_t bytes_unit = (size_t)unit * fine_cells(p) * sizeof(float2);
+  if (p.budget == 0) {
+    *per = units;
+    return SDN_OK;
+  }
+  const size_t n = p.budget / bytes_unit;
+  if (n < 1)
+    return fail(SDN_E_NOMEM, std::string(fn) + ": workspace budget below one coil's grids");
+  *per = (int)std::min<size_t>(n, (size_t)units);
+  return SDN_OK;
+}
+
+#define SDN_TRY(expr)                      \
+  do {                                     \
+    sdn_status _s = (expr);                \
+    if (_s != SDN_OK) return _s;           \
+  } while (0)
+#define SDN_HIP(expr, what) SDN_TRY(hip_check((expr), what))
+
+sdn_status check_mrf_args(const sdn_plan_s &p, const char *fn, const void *x, int K,
+                          const void *smaps, int C, const int32_t *coil_idx, int B,
+                          const void *V, const void *y) {
+  if (K < 1 || K > kMaxK) return fail(SDN_E_INVALID, std::string(fn) + ": K must be in [1, 8]");
+  if (B < 1 || B > kMaxB) return fail(SDN_E_INVALID, std::string(fn) + ": B must be in [1, 64]");
+  if (C < 1) return fail(SDN_E_INVALID, std::string(fn) + ": C must be >= 1");
+  if (!x || !smaps || !coil_idx || !V)
+    return fail(SDN_E_INVALID, std::string(fn) + ": null array argument");
+  if (!y && p.M > 0) return fail(SDN_E_INVALID, std::string(fn) + ": null k-space argument");
+  for (int b = 0; b < B; ++b)
+    if (coil_idx[b] < 0 || coil_idx[b] >= C)
+      return fail(SDN_E_RANGE, std::string(fn) + ": coil index outside [0, C)");
+  if (p.ax[0].nf / K < 2)
+    return fail(SDN_E_UNSUPPORTED, std::string(fn) + ": too many channels for this grid");
+  return SDN_OK;
+}
+
+CoilList coil_list(const int32_t *idx, int b0, int n) {
+  CoilList c{};
+  for (int i = 0; i < n; ++i) c.idx[i] = idx[b0 + i];
+  return c;
+}
+
+// forward stages for one chunk of coils: grid <- FFT3(pad(deapod(S x)))
+sdn_status forward_grid(sdn_plan_s *p, const float2 *x, int K, const float2 *smaps,
+                        const CoilList &coils, int B, hipStream_t st) {
+  const int P = B * K;
+  SDN_HIP(launch_pre_fftx(*p, x, K, smaps, coils, B, p->grid, st), "forward x pass");
+  SDN_HIP(launch_fft_axis(*p, p->grid, P, 1, false, true, false, st), "forward y pass");
+  SDN_HIP(launch_fft_axis(*p, p->grid, P, 2, false, true, false, st), "forward z pass");
+  return SDN_OK;
+}
+
+// adjoint stages after spreading: x_out (+)= sum_b conj(S_b) crop(IFFT3(grid)) / deapod
+sdn_status adjoint_grid(sdn_plan_s *p, int K, const float2 *smaps, const CoilList &coils, int B,
+                        float2 *xout, int accumulate, hipStream_t st) {
+  const int P = B * K;
+  SDN_HIP(launch_fft_axis(*p, p->grid, P, 2, true, false, true, st), "adjoint z pass");
+  SDN_HIP(launch_fft_axis(*p, p->grid, P, 1, true, false, true, st), "adjoint y pass");
+  SDN_HIP(launch_post_ifftx(*p, p->grid, K, smaps, coils, B, xout, accumulate, st),
+          "adjoint x pass");
+  return SDN_OK;
+}
+
+__global__ void k_zero_c64(float2 *a, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    a[i] = make_float2(0.f, 0.f);
+}
+
+sdn_status zero_user(float2 *a, size_t n, hipStream_t st) {
+  if (n == 0) return SDN_OK;
+  const unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 1u << 16);
+  hipLaunchKernelGGL(k_zero_c64, dim3(blocks), dim3(256), 0, st, a, n);
+  return hip_check(hipGetLastError(), "zero fill");
+}
+
+}  // namespace
+
+extern "C" {
+
+sdn_status sdn_forward(sdn_plan p, const void *img, void *ksp, int batch, void *stream) {
+  SDN_TRY(check_plan(p, "sdn_forward"));
+  if (batch < 0) return fail(SDN_E_INVALID, "sdn_forward: batch < 0");
+  if (batch == 0 || p->M == 0) return SDN_OK;
+  if (!img || !ksp) return fail(SDN_E_INVALID, "sdn_forward: null array argument");
+  hipStream_t st = (hipStream_t)stream;
+  int per;
+  SDN_TRY(channels_per_pass(*p, 1, batch, &per, "sdn_forward"));
+  const int cap = std::max(1, 8192 / p->ax[0].nf - 1);
+  per = std::min(per, std::max(1, cap));
+  const size_t nvox = image_voxels(*p);
+  CoilList one{};
+  for (int c0 = 0; c0 < batch; c0 += per) {
+    const int pc = std::min(per, batch - c0);
+    SDN_TRY(ensure_grid(p, (size_t)pc * fine_cells(*p)));
+    SDN_TRY(forward_grid(p, (const float2 *)img + c0 * nvox, pc, nullptr, one, 1, st));
+    InterpArgs a{};
+    a.grid = p->grid;
+    a.P = pc;
+    a.groups = pc;
+    a.kg = 1;
+    a.y = (float2 *)ksp + (size_t)c0 * p->M;
+    SDN_HIP(launch_interp(*p, a, st), "interpolation");
+  }
+  return SDN_OK;
+}
+
+sdn_status sdn_adjoint(sdn_plan p, const void *ksp, void *img, int batch, void *stream) {
+  SDN_TRY(check_plan(p, "sdn_adjoint"));
+  if (batch < 0) return fail(SDN_E_INVALID, "sdn_adjoint: batch < 0");
+  if (batch == 0) return SDN_OK;
+  if (!img || (!ksp && p->M > 0)) return fail(SDN_E_INVALID, "sdn_adjoint: null array argument");
+  hipStream_t st = (hipStream_t)stream;
+  const size_t nvox = image_voxels(*p);
+  if (p->M == 0) return zero_user((float2 *)img, (size_t)batch * nvox, st);
+  int per;
+  SDN_TRY(channels_per_pass(*p, 1, batch, &per, "sdn_adjoint"));
+  const int cap = std::max(1, 8192 / p->ax[0].nf - 1);
+  per = std::min(per, cap);
+  CoilList one{};
+  for (int c0 = 0; c0 < batch; c0 += per) {
+    const int pc = std::min(per, batch - c0);
+    const size_t cells = (size_t)pc * fine_cells(*p);
+    SDN_TRY(ensure_grid(p, cells));
+    SDN_HIP(launch_fill_zero(p->grid, cells, st), "grid clear");
+    SpreadArgs s{};
+    s.grid = p->grid;
+    s.P = pc;
+    s.K = 1;
+    s.V = nullptr;
+    s.src = (const float2 *)ksp + (size_t)c0 * p->M;
+    s.src_plan_order = false;
+    SDN_HIP(launch_spread(*p, s, st), "spreading");
+    SDN_TRY(adjoint_grid(p, pc, nullptr, one, 1, (float2 *)img + c0 * nvox, 0, st));
+  }
+  return SDN_OK;
+}
+
+sdn_status sdn_mrf_forward(sdn_plan p, const void *x, int K, const void *smaps, int C,
+                           const int32_t *coil_idx, int B, const void *V, void *y,
+                           void *stream) {
+  SDN_TRY(check_plan(p, "sdn_mrf_forward"));
+  SDN_TRY(check_mrf_args(*p, "sdn_mrf_forward", x, K, smaps, C, coil_idx, B, V, y));
+  if (p->M == 0) return SDN_OK;
+  hipStream_t st = (hipStream_t)stream;
+  int per;
+  SDN_TRY(channels_per_pass(*p, K, B, &per, "sdn_mrf_forward"));
+  for (int b0 = 0; b0 < B; b0 += per) {
+    const int bc = std::min(per, B - b0);
+    const CoilList coils = coil_list(coil_idx, b0, bc);
+    SDN_TRY(ensure_grid(p, (size_t)bc * K * fine_cells(*p)));
+    SDN_TRY(forward_grid(p, (const float2 *)x, K, (const float2 *)smaps, coils, bc, st));
+    InterpArgs a{};
+    a.grid = p->grid;
+    a.P = bc * K;
+    a.groups = bc;
+    a.kg = K;
+    a.V = (const float2 *)V;
+    a.y = (float2 *)y + (size_t)b0 * p->M;
+    SDN_HIP(launch_interp(*p, a, st), "interpolation");
+  }
+  return SDN_OK;
+}
+
+sdn_status sdn_mrf_adjoint(sdn_plan p, const void *y, int K, const void *smaps, int C,
+                           const int32_t *coil_idx, int B, const void *V, void *x_out,
+                           int accumulate, void *stream) {
+  SDN_TRY(check_plan(p, "sdn_mrf_adjoint"));
+  SDN_TRY(check_mrf_args(*p, "sdn_mrf_adjoint", x_out, K, smaps, C, coil_idx, B, V, y));
+  hipStream_t st = (hipStream_t)stream;
+  if (p->M == 0) {
+    if (!accumulate) return zero_user((float2 *)x_out, (size_t)K * image_voxels(*p), st);
+    return SDN_OK;
+  }
+  int per;
+  SDN_TRY(channels_per_pass(*p, K, B, &per, "sdn_mrf_adjoint"));
+  for (int b0 = 0; b0 < B; b0 += per) {
+    const int bc = std::min(per, B - b0);
+    const CoilList coils = coil_list(coil_idx, b0, bc);
+    const size_t cells = (size_t)bc * K * fine_cells(*p);
+    SDN_TRY(ensure_grid(p, cells));
+    SDN_HIP(launch_fill_zero(p->grid, cells, st), "grid clear");
+    SpreadArgs s{};
+    s.grid = p->grid;
+    s.P = bc * K;
+    s.K = K;
+    s.V = (const float2 *)V;
+    s.src = (const float2 *)y + (size_t)b0 * p->M;
+    s.src_plan_order = false;
+    SDN_HIP(launch_spread(*p, s, st), "spreading");
+    SDN_TRY(adjoint_grid(p, K, (const float2 *)smaps, coils, bc, (float2 *)x_out,
+                         (accumulate || b0 > 0) ? 1 : 0, st));
+  }
+  return SDN_OK;
+}
+
+sdn_status sdn_mrf_dc_grad(sdn_plan p, const void *x, int K, const void *smaps, int C,
+                           const int32_t *coil_idx, int B, const void *V, const void *d,
+                           const float *w, double *loss, void *grad, void *stream) {
+  SDN_TRY(check_plan(p, "sdn_mrf_dc_grad"));
+  SDN_TRY(check_mrf_args(*p, "sdn_mrf_dc_grad", x, K, smaps, C, coil_idx, B, V, d));
+  if (!loss || !grad) return fail(SDN_E_INVALID, "sdn_mrf_dc_grad: null output argument");
+  hipStream_t st = (hipStream_t)stream;
+  SDN_HIP(launch_fill_zero_f64(loss, 1, st), "loss clear");
+  if (p->M == 0) return zero_user((float2 *)grad, (size_t)K * image_voxels(*p), st);
+  int per;
+  SDN_TRY(channels_per_pass(*p, K, B, &per, "sdn_mrf_dc_grad"));
+  SDN_TRY(ensure_kbuf(p, (size_t)per * p->M));
+  for (int b0 = 0; b0 < B; b0 += per) {
+    const int bc = std::min(per, B - b0);
+    const CoilList coils = coil_list(coil_idx, b0, bc);
+    const size_t cells = (size_t)bc * K * fine_cells(*p);
+    SDN_TRY(ensure_grid(p, cells));
+    SDN_TRY(forward_grid(p, (const float2 *)x, K, (const float2 *)smaps, coils, bc, st));
+    InterpArgs a{};
+    a.grid = p->grid;
+    a.P = bc * K;
+    a.groups = bc;
+    a.kg = K;
+    a.V = (const float2 *)V;
+    a.d = (const float2 *)d + (size_t)b0 * p->M;
+    a.w = w;
+    a.r_plan = p->kbuf;
+    a.loss = loss;
+    SDN_HIP(launch_interp(*p, a, st), "interpolation + residual");
+    SDN_HIP(launch_fill_zero(p->grid, cells, st), "grid clear");
+    SpreadArgs s{};
+    s.grid = p->grid;
+    s.P = bc * K;
+    s.K = K;
+    s.V = (const float2 *)V;
+    s.src = p->kbuf;
+    s.src_plan_order = true;
+    SDN_HIP(launch_spread(*p, s, st), "spreading");
+    SDN_TRY(adjoint_grid(p, K, (const float2 *)smaps, coils, bc, (float2 *)grad, b0 > 0 ? 1 : 0,
+                         st));
+  }
+  return SDN_OK;
+}
+
+sdn_status sdn_mrf_forward_plain(sdn_plan p, const void *x, int K, const void *smaps, int C,
+                                 const int32_t *coil_idx, int B, const void *V, void *y,
+                                 void *stream) {
+  SDN_TRY(check_plan(p, "sdn_mrf_forward_plain"));
+  SDN_TRY(check_mrf_args(*p, "sdn_mrf_forward_plain", x, K, smaps, C, coil_idx, B, V, y));
+  if (p->M == 0) return SDN_OK;
+  hipStream_t st = (hipStream_t)stream;
+  const size_t nvox = image_voxels(*p);
+  SDN_TRY(ensure_grid(p, fine_cells(*p)));
+  SDN_TRY(ensure_kbuf(p, (size_t)p->M));
+  for (int b = 0; b < B; ++b) {
+    const CoilList coil = coil_list(coil_idx, b, 1);
+    for (int k = 0; k < K; ++k) {
+      SDN_TRY(forward_grid(p, (const float2 *)x + k * nvox, 1, (const float2 *)smaps, coil, 1, st));
+      InterpArgs a{};
+      a.grid = p->grid;
+      a.P = 1;
+      a.groups = 1;
+      a.kg = 1;
+      a.y = p->kbuf;
+      SDN_HIP(launch_interp(*p, a, st), "interpolation");
+      SDN_HIP(launch_mix_fwd(*p, p->kbuf, (const float2 *)V, K, k, (float2 *)y + (size_t)b * p->M,
+                             k > 0 ? 1 : 0, st),
+              "subspace mix");
+    }
+  }
+  return SDN_OK;
+}
+
+sdn_status sdn_mrf_adjoint_plain(sdn_plan p, const void *y, int K, const void *smaps, int C,
+                                 const int32_t *coil_idx, int B, const void *V, void *x_out,
+                                 int accumulate, void *stream) {
+  SDN_TRY(check_plan(p, "sdn_mrf_adjoint_plain"));
+  SDN_TRY(check_mrf_args(*p, "sdn_mrf_adjoint_plain", x_out, K, smaps, C, coil_idx, B, V, y));
+  hipStream_t st = (hipStream_t)stream;
+  const size_t nvox = image_voxels(*p);
+  if (p->M == 0) {
+    if (!accumulate) return zero_user((float2 *)x_out, (size_t)K * nvox, st);
+    return SDN_OK;
+  }
+  SDN_TRY(ensure_grid(p, fine_cells(*p)));
+  SDN_TRY(ensure_kbuf(p, (size_t)p->M));
+  for (int b = 0; b < B; ++b) {
+    const CoilList coil = coil_list(coil_idx, b, 1);
+    for (int k = 0; k < K; ++k) {
+      SDN_HIP(launch_mix_adj(*p, (const float2 *)y + (size_t)b * p->M, (const float2 *)V, K, k,
+                             p->kbuf, st),
+              "subspace mix");
+      SDN_HIP(launch_fill_zero(p->grid, fine_cells(*p), st), "grid clear");
+      SpreadArgs s{};
+      s.grid = p->grid;
+      s.P = 1;
+      s.K = 1;
+      s.V = nullptr;
+      s.src = p->kbuf;
+      s.src_plan_order = false;
+      SDN_HIP(launch_spread(*p, s, st), "spreading");
+      SDN_TRY(adjoint_grid(p, 1, (const float2 *)smaps, coil, 1, (float2 *)x_out + k * nvox,
+                           (accumulate || b > 0) ? 1 : 0, st));
+    }
+  }
+  return SDN_OK;
+}
+
+sdn_status sdn_workspace_size(sdn_plan p, int B, int K, size_t *bytes) {
+  SDN_TRY(check_plan(p, "sdn_workspace_size"));
+  if (!bytes || B < 1 || K < 1) return fail(SDN_E_INVALID, "sdn_workspace_size: bad argument");
+  int per;
+  SDN_TRY(channels_per_pass(*p, K, B, &per, "sdn_workspace_size"));
+  *bytes = ((size_t)per * K * fine_cells(*p) + (size_t)per * p->M) * sizeof(float2);
+  return SDN_OK;
+}
+
+sdn_status sdn_release_workspace(sdn_plan p) {
+  SDN_TRY(check_plan(p, "sdn_release_workspace"));
+  if (p->grid) (void)hipFree(p->grid);
+  if (p->kbuf) (void)hipFree(p->kbuf);
+  p->grid = nullptr;
+  p->kbuf = nullptr;
+  p->grid_cap = p->kbuf_cap = 0;
+  return SDN_OK;
+}
+
+}  // extern "C"

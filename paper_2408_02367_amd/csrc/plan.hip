@@ -1,0 +1,330 @@
+// Plan construction: fold and quantise the trajectory, bin the points into
+// fine-grid tiles and sort them tile by tile (a counting sort: histogram,
+// exclusive scan, scatter), then split crowded tiles into work items.
+//
+// The trajectory of an MRF scan is fixed for every data-consistency step of
+// the reconstruction (Sec. 3: thousands of iterations over one scan), so
+// this runs once and everything per-step reads the sorted records.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "sdn_internal.h"
+
+namespace sdn {
+const char *last_error();
+}
+
+using namespace sdn;
+
+namespace {
+
+constexpr float kMaxAbsCoord = 1048576.0f;   // 2^20 radians
+
+struct FoldGeom {
+  int nf[3];
+  int tile[3];
+  int ntile[3];
+  int W;
+  int T;
+};
+
+// One thread per point.  Fine coordinate s = k nf / (2 pi) in FP64; the W
+// nodes of the point are l0 .. l0+W-1 with l0 = floor(s - W/2) + 1 (the
+// half-open rule s - W/2 < l <= s + W/2) and fractional offset
+// t = (s - W/2) - floor(s - W/2) in [0, 1).  l0 is wrapped into [0, nf),
+// which is exact because the fine grid is periodic.
+__global__ void k_fold(const float *__restrict__ traj, int M, FoldGeom g,
+                       const int32_t *__restrict__ frame, int *__restrict__ key,
+                       float4 *__restrict__ rec, int *__restrict__ count, int *__restrict__ bad) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= M) return;
+  int l0[3];
+  float t[3];
+  bool ok = true;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const float k = traj[3 * (size_t)j + d];
+    if (!(fabsf(k) <= kMaxAbsCoord)) ok = false;   // also catches NaN
+    const double s = (double)k * ((double)g.nf[d] / (2.0 * M_PI));
+    const double a = s - 0.5 * g.W;
+    const double fl = floor(a);
+    t[d] = (float)(a - fl);
+    double l = fl + 1.0;
+    l -= (double)g.nf[d] * floor(l / (double)g.nf[d]);
+    int li = (int)l;
+    if (li >= g.nf[d]) li -= g.nf[d];
+    if (li < 0) li += g.nf[d];
+    l0[d] = li;
+  }
+  if (frame) {
+    const int f = frame[j];
+    if (f < 0 || f >= g.T) atomicOr(bad, 2);
+  }
+  if (!ok) {
+    atomicOr(bad, 1);
+    key[j] = 0;
+    l0[0] = l0[1] = l0[2] = 0;
+    t[0] = t[1] = t[2] = 0.f;
+  }
+  const int tx = l0[0] / g.tile[0], ty = l0[1] / g.tile[1], tz = l0[2] / g.tile[2];
+  const int kk = (tz * g.ntile[1] + ty) * g.ntile[0] + tx;
+  key[j] = kk;
+  const unsigned packed = (unsigned)l0[0] | ((unsigned)l0[1] << 10) | ((unsigned)l0[2] << 20);
+  rec[j] = make_float4(t[0], t[1], t[2], __uint_as_float(packed));
+  atomicAdd(&count[kk], 1);
+}
+
+__global__ void k_scatter(const int *__restrict__ key, const float4 *__restrict__ rec_tmp,
+                          const int32_t *__restrict__ frame, int M,
+                          const int *__restrict__ offset, int *__restrict__ cursor,
+                          float4 *__restrict__ rec, int2 *__restrict__ pidx) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= M) return;
+  const int k = key[j];
+  const int pos = offset[k] + atomicAdd(&cursor[k], 1);
+  rec[pos] = rec_tmp[j];
+  pidx[pos] = make_int2(frame ? frame[j] : 0, j);
+}
+
+void free_plan_memory(sdn_plan_s *p) {
+  for (int d = 0; d < 3; ++d) {
+    if (p->dinv[d]) (void)hipFree(p->dinv[d]);
+    if (p->tw[d]) (void)hipFree(p->tw[d]);
+    p->dinv[d] = nullptr;
+    p->tw[d] = nullptr;
+  }
+  if (p->rec) (void)hipFree(p->rec);
+  if (p->pidx) (void)hipFree(p->pidx);
+  if (p->frame_user) (void)hipFree(p->frame_user);
+  if (p->work) (void)hipFree(p->work);
+  if (p->grid) (void)hipFree(p->grid);
+  if (p->kbuf) (void)hipFree(p->kbuf);
+  p->rec = nullptr;
+  p->pidx = nullptr;
+  p->frame_user = nullptr;
+  p->work = nullptr;
+  p->grid = nullptr;
+  p->kbuf = nullptr;
+  p->grid_cap = p->kbuf_cap = 0;
+}
+
+template <typename T>
+sdn_status dalloc(T **ptr, size_t n, const char *what) {
+  *ptr = nullptr;
+  if (n == 0) return SDN_OK;
+  return hip_check(hipMalloc((void **)ptr, n * sizeof(T)), what);
+}
+
+}  // namespace
+
+extern "C" {
+
+void sdn_default_opts(sdn_opts *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->W = 6;
+  o->sigma = 2.0;
+  o->tile = 0;
+  o->max_points_per_item = 0;
+  o->workspace_budget = 0;
+}
+
+const char *sdn_last_error(void) { return sdn::last_error(); }
+
+sdn_status sdn_plan_create(sdn_plan *out, const int64_t shape[3], const float *traj,
+                           int64_t M, const int32_t *frame_of_point, int32_t T,
+                           const sdn_opts *opts, void *stream) {
+  if (!out) return fail(SDN_E_INVALID, "sdn_plan_create: out is NULL");
+  *out = nullptr;
+  if (!shape) return fail(SDN_E_INVALID, "sdn_plan_create: shape is NULL");
+  sdn_opts o;
+  sdn_default_opts(&o);
+  if (opts) o = *opts;
+  if (o.W != 4 && o.W != 6 && o.W != 8)
+    return fail(SDN_E_UNSUPPORTED, "sdn_plan_create: W must be 4, 6 or 8");
+  if (!(o.sigma >= 1.25 && o.sigma <= 4.0))
+    return fail(SDN_E_INVALID, "sdn_plan_create: sigma must be in [1.25, 4]");
+  if (M < 0 || M > (int64_t)INT32_MAX - 1024)
+    return fail(SDN_E_INVALID, "sdn_plan_create: M out of range [0, 2^31)");
+  if (M > 0 && !traj) return fail(SDN_E_INVALID, "sdn_plan_create: traj is NULL");
+  if (frame_of_point && T < 1)
+    return fail(SDN_E_INVALID, "sdn_plan_create: frame_of_point given with T < 1");
+  if (T < 0) return fail(SDN_E_INVALID, "sdn_plan_create: T < 0");
+  for (int d = 0; d < 3; ++d)
+    if (shape[d] < 1 || shape[d] > 4096)
+      return fail(SDN_E_INVALID, "sdn_plan_create: image sizes must be in [1, 4096]");
+  const double beta = kb_beta(o.W, o.sigma);
+  if (!(M_PI * o.W / (2.0 * o.sigma) < beta))
+    return fail(SDN_E_UNSUPPORTED, "sdn_plan_create: kernel too wide for this sigma");
+
+  hipStream_t st = (hipStream_t)stream;
+  sdn_plan_s *p = new sdn_plan_s();
+  p->magic = kPlanMagic;
+  (void)hipGetDevice(&p->device);
+  p->M = M;
+  p->T = frame_of_point ? T : (T < 1 ? 1 : T);
+  p->W = o.W;
+  p->sigma = o.sigma;
+  p->beta = beta;
+  p->ncoef = kernel_ncoef(o.W);
+  kernel_coefficients(o.W, beta, p->ncoef, &p->coef);
+  p->budget = o.workspace_budget;
+  p->max_points_per_item = o.max_points_per_item > 0 ? o.max_points_per_item : 1024;
+
+  const int tile_edge = o.tile > 0 ? o.tile : 8;
+  // shape is (Nz, Ny, Nx); axis 0 = x
+  for (int d = 0; d < 3; ++d) {
+    Axis &a = p->ax[d];
+    a.N = (int)shape[2 - d];
+    a.nf = fine_size(a.N, o.sigma, o.W);
+    a.half = a.N / 2;
+    a.tile = std::min(tile_edge, a.nf);
+    a.ntile = (a.nf + a.tile - 1) / a.tile;
+    p->rp[d] = radix_plan(a.nf);
+    if (a.nf > 1024 || p->rp[d].n <= 0) {
+      delete p;
+      return fail(SDN_E_UNSUPPORTED, "sdn_plan_create: fine grid above 1024 per axis");
+    }
+  }
+
+  sdn_status s = SDN_OK;
+  for (int d = 0; d < 3 && s == SDN_OK; ++d) {
+    auto di = deapod_inverse(p->ax[d].N, p->ax[d].nf, p->W, beta);
+    auto tw = twiddles(p->ax[d].nf);
+    s = dalloc(&p->dinv[d], di.size(), "plan tables");
+    if (s == SDN_OK) s = dalloc(&p->tw[d], (size_t)p->ax[d].nf, "plan tables");
+    if (s == SDN_OK)
+      s = hip_check(hipMemcpy(p->dinv[d], di.data(), di.size() * 4, hipMemcpyHostToDevice),
+                    "plan tables upload");
+    if (s == SDN_OK)
+      s = hip_check(hipMemcpy(p->tw[d], tw.data(), tw.size() * 4, hipMemcpyHostToDevice),
+                    "plan tables upload");
+  }
+  p->nbins = (int64_t)p->ax[0].ntile * p->ax[1].ntile * p->ax[2].ntile;
+
+  int *key = nullptr, *count = nullptr, *cursor = nullptr, *offset = nullptr, *bad = nullptr;
+  float4 *rec_tmp = nullptr;
+  if (s == SDN_OK && M > 0) {
+    const int m = (int)M;
+    const int nb = (int)p->nbins;
+    s = dalloc(&key, m, "plan sort");
+    if (s == SDN_OK) s = dalloc(&rec_tmp, m, "plan sort");
+    if (s == SDN_OK) s = dalloc(&count, nb, "plan sort");
+    if (s == SDN_OK) s = dalloc(&cursor, nb, "plan sort");
+    if (s == SDN_OK) s = dalloc(&offset, nb, "plan sort");
+    if (s == SDN_OK) s = dalloc(&bad, 1, "plan sort");
+    if (s == SDN_OK) s = dalloc(&p->rec, m, "plan points");
+    if (s == SDN_OK) s = dalloc(&p->pidx, m, "plan points");
+    if (s == SDN_OK && frame_of_point) {
+      s = dalloc(&p->frame_user, m, "plan points");
+      if (s == SDN_OK)
+        s = hip_check(hipMemcpyAsync(p->frame_user, frame_of_point, (size_t)m * 4,
+                                     hipMemcpyDeviceToDevice, st),
+                      "plan frame copy");
+    }
+    if (s == SDN_OK) s = hip_check(hipMemsetAsync(count, 0, (size_t)nb * 4, st), "plan memset");
+    if (s == SDN_OK) s = hip_check(hipMemsetAsync(cursor, 0, (size_t)nb * 4, st), "plan memset");
+    if (s == SDN_OK) s = hip_check(hipMemsetAsync(bad, 0, 4, st), "plan memset");
+    FoldGeom g;
+    for (int d = 0; d < 3; ++d) {
+      g.nf[d] = p->ax[d].nf;
+      g.tile[d] = p->ax[d].tile;
+      g.ntile[d] = p->ax[d].ntile;
+    }
+    g.W = p->W;
+    g.T = p->T;
+    if (s == SDN_OK) {
+      hipLaunchKernelGGL(k_fold, dim3((m + 255) / 256), dim3(256), 0, st, traj, m, g,
+                         frame_of_point, key, rec_tmp, count, bad);
+      s = hip_check(hipGetLastError(), "plan fold kernel");
+    }
+    std::vector<int> hcount(nb);
+    int hbad = 0;
+    if (s == SDN_OK)
+      s = hip_check(hipMemcpyAsync(hcount.data(), count, (size_t)nb * 4, hipMemcpyDeviceToHost, st),
+                    "plan histogram download");
+    if (s == SDN_OK)
+      s = hip_check(hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, st), "plan flag download");
+    if (s == SDN_OK) s = hip_check(hipStreamSynchronize(st), "plan sync");
+    if (s == SDN_OK && (hbad & 1))
+      s = fail(SDN_E_RANGE, "sdn_plan_create: non-finite coordinate or |k| > 2^20");
+    if (s == SDN_OK && (hbad & 2))
+      s = fail(SDN_E_RANGE, "sdn_plan_create: frame_of_point outside [0, T)");
+    std::vector<int> hoff(nb);
+    std::vector<int4> items;
+    if (s == SDN_OK) {
+      int64_t acc = 0;
+      const int cap = p->max_points_per_item;
+      for (int b = 0; b < nb; ++b) {
+        hoff[b] = (int)acc;
+        const int c = hcount[b];
+        p->max_bin = std::max<int64_t>(p->max_bin, c);
+        for (int st0 = 0; st0 < c; st0 += cap)
+          items.push_back(make_int4(b, (int)acc + st0, std::min(cap, c - st0), 0));
+        acc += c;
+      }
+      // crowded tiles first: they finish last otherwise
+      std::stable_sort(items.begin(), items.end(),
+                       [](const int4 &a, const int4 &b) { return a.z > b.z; });
+      p->nwork = (int64_t)items.size();
+      s = dalloc(&p->work, items.size(), "plan work list");
+      if (s == SDN_OK)
+        s = hip_check(hipMemcpyAsync(offset, hoff.data(), (size_t)nb * 4, hipMemcpyHostToDevice, st),
+                      "plan offsets upload");
+      if (s == SDN_OK && !items.empty())
+        s = hip_check(hipMemcpyAsync(p->work, items.data(), items.size() * sizeof(int4),
+                                     hipMemcpyHostToDevice, st),
+                      "plan work upload");
+    }
+    if (s == SDN_OK) {
+      hipLaunchKernelGGL(k_scatter, dim3((m + 255) / 256), dim3(256), 0, st, key, rec_tmp,
+                         frame_of_point, m, offset, cursor, p->rec, p->pidx);
+      s = hip_check(hipGetLastError(), "plan scatter kernel");
+    }
+    if (s == SDN_OK) s = hip_check(hipStreamSynchronize(st), "plan sync");
+  }
+  for (void *q : {(void *)key, (void *)rec_tmp, (void *)count, (void *)cursor, (void *)offset,
+                  (void *)bad})
+    if (q) (void)hipFree(q);
+  if (s != SDN_OK) {
+    free_plan_memory(p);
+    p->magic = 0;
+    delete p;
+    return s;
+  }
+  *out = p;
+  return SDN_OK;
+}
+
+sdn_status sdn_plan_destroy(sdn_plan p) {
+  if (!p) return SDN_OK;
+  if (p->magic != kPlanMagic) return fail(SDN_E_STATE, "sdn_plan_destroy: not a live plan");
+  free_plan_memory(p);
+  p->magic = 0;
+  delete p;
+  return SDN_OK;
+}
+
+sdn_status sdn_plan_get_info(sdn_plan p, sdn_plan_info *info) {
+  if (!p || p->magic != kPlanMagic) return fail(SDN_E_STATE, "sdn_plan_get_info: not a live plan");
+  if (!info) return fail(SDN_E_INVALID, "sdn_plan_get_info: info is NULL");
+  std::memset(info, 0, sizeof(*info));
+  for (int d = 0; d < 3; ++d) {
+    info->shape[2 - d] = p->ax[d].N;
+    info->fine[2 - d] = p->ax[d].nf;
+    info->tile[2 - d] = p->ax[d].tile;
+  }
+  info->M = p->M;
+  info->T = p->T;
+  info->W = p->W;
+  info->sigma = p->sigma;
+  info->beta = p->beta;
+  info->nbins = p->nbins;
+  info->nwork = p->nwork;
+  info->max_bin = p->max_bin;
+  info->ncoef = p->ncoef;
+  return SDN_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,163 @@
+// Internal declarations of the stodip_nufft library (host + device).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/stodip_nufft.h"
+
+namespace sdn {
+
+constexpr int kMaxW = 8;        // widest kernel supported
+constexpr int kMaxCoef = 16;    // polynomial coefficients per kernel piece
+constexpr int kMaxB = 64;       // coils per minibatch
+constexpr int kMaxK = 8;        // subspace channels
+constexpr int kMaxRadices = 12; // FFT passes per axis
+
+// Piecewise-polynomial Kaiser-Bessel kernel: for a point with fractional
+// offset t in [0,1), the weight of its i-th node is
+//   sum_d c[i][d] z^d,  z = 2t - 1.
+struct KerCoef {
+  float c[kMaxW][kMaxCoef];
+};
+
+// Radix decomposition of one FFT length.
+struct RadixPlan {
+  int L;
+  int n;
+  int r[kMaxRadices];
+};
+
+// Coil indices of a minibatch, passed by value to kernels.
+struct CoilList {
+  int idx[kMaxB];
+};
+
+// Per-axis deapodisation tables and geometry (x = 0, y = 1, z = 2).
+struct Axis {
+  int N;      // image length
+  int nf;     // fine length
+  int half;   // floor(N / 2)
+  int tile;   // tile edge
+  int ntile;  // tiles along the axis
+};
+
+// Every status-returning path records a message through this.
+sdn_status fail(sdn_status s, const std::string &msg);
+sdn_status hip_check(hipError_t e, const char *what);
+
+// ---------------------------------------------------------------- host math
+double kb_beta(int W, double sigma);
+double bessel_i0(double x);
+double kb_phi(double u, int W, double beta);
+double kb_phi_hat(double xi, int W, double beta);
+int fine_size(int64_t n, double sigma, int W);
+bool smooth7(int64_t n);
+int kernel_ncoef(int W);
+void kernel_coefficients(int W, double beta, int ncoef, KerCoef *out);
+RadixPlan radix_plan(int L);
+std::vector<float> deapod_inverse(int N, int nf, int W, double beta);
+std::vector<float> twiddles(int L);
+
+}  // namespace sdn
+
+// The plan object behind the opaque handle.
+struct sdn_plan_s {
+  uint32_t magic;
+  int device;
+  sdn::Axis ax[3];          // x, y, z
+  int64_t M;
+  int32_t T;
+  int W;
+  double sigma, beta;
+  int ncoef;
+  sdn::KerCoef coef;
+  sdn::RadixPlan rp[3];     // x, y, z
+  int max_points_per_item;
+  size_t budget;
+
+  // device tables
+  float *dinv[3] = {nullptr, nullptr, nullptr};   // 1/phi_hat per image index
+  float2 *tw[3] = {nullptr, nullptr, nullptr};    // exp(-2 pi i m / nf)
+
+  // points in plan (tile-sorted) order
+  float4 *rec = nullptr;     // (tx, ty, tz, bits of packed l0)
+  int2 *pidx = nullptr;      // (frame, original index)
+  int32_t *frame_user = nullptr;  // frame per point, user order
+  int4 *work = nullptr;      // (tile, start, count, 0)
+  int64_t nbins = 0, nwork = 0, max_bin = 0;
+
+  // workspace
+  float2 *grid = nullptr;
+  size_t grid_cap = 0;       // complex elements
+  float2 *kbuf = nullptr;    // k-space scratch (residual / plain path)
+  size_t kbuf_cap = 0;
+};
+
+constexpr uint32_t kPlanMagic = 0x5d4e5546u;
+
+namespace sdn {
+
+// ----------------------------------------------------------- kernel launchers
+// (defined in the .hip files; all enqueue on `st`)
+hipError_t launch_fold(const sdn_plan_s &p, const float *traj, int64_t M, int *key,
+                       float4 *rec_tmp, int *count, int *bad, hipStream_t st);
+hipError_t launch_scatter(const sdn_plan_s &p, const int *key, const float4 *rec_tmp,
+                          const int32_t *frame, int64_t M, const int *offset, int *cursor,
+                          hipStream_t st);
+
+hipError_t launch_fill_zero(float2 *a, size_t n, hipStream_t st);
+hipError_t launch_fill_zero_f64(double *a, size_t n, hipStream_t st);
+
+// Forward x-pass fused with coil multiply, deapodisation and zero padding.
+// Channels p = b*K + k, chunk [p0, p0 + pc) of P = B*K.
+hipError_t launch_pre_fftx(const sdn_plan_s &p, const float2 *x, int K, const float2 *smaps,
+                           const CoilList &coils, int B, float2 *grid, hipStream_t st);
+// Adjoint x-pass fused with crop, deapodisation, conj coil multiply and the
+// sum over coils.
+hipError_t launch_post_ifftx(const sdn_plan_s &p, const float2 *grid, int K,
+                             const float2 *smaps, const CoilList &coils, int B, float2 *xout,
+                             int accumulate, hipStream_t st);
+// Strided y or z pass over P channels; inverse = +i sign.
+// axis 1 = y, 2 = z.  prune_in / prune_out: only the N image rows are read /
+// written (the others are known zeros / not needed).
+hipError_t launch_fft_axis(const sdn_plan_s &p, float2 *grid, int P, int axis, bool inverse,
+                           bool prune_in, bool prune_out, hipStream_t st);
+
+// Interpolation (type 2) + optional subspace mix and DC epilogue.
+struct InterpArgs {
+  const float2 *grid;
+  int P;          // channels in the grid
+  int groups;     // output rows (coils for the mix, channels otherwise)
+  int kg;         // channels per group
+  const float2 *V;  // [T][K] or null (no mix: kg = 1)
+  float2 *y;        // [groups][M] user order (may be null in DC mode)
+  // DC epilogue: r = 2 w (y - d) in plan order, loss += w |y - d|^2
+  const float2 *d;  // [groups][M] user order, or null
+  const float *w;   // [M] user order, or null
+  float2 *r_plan;   // [groups][M] plan order
+  double *loss;
+};
+hipError_t launch_interp(const sdn_plan_s &p, const InterpArgs &a, hipStream_t st);
+
+// Spreading (type 1) of k-space values onto P fine grids (grid is added to).
+struct SpreadArgs {
+  float2 *grid;
+  int P;
+  int K;              // channels per coil for the conj(V) mix (mix mode)
+  const float2 *V;    // [T][K] or null: no mix, channel p reads src row p
+  const float2 *src;  // [rows][M]
+  bool src_plan_order;
+};
+hipError_t launch_spread(const sdn_plan_s &p, const SpreadArgs &a, hipStream_t st);
+
+// Plain-path subspace mix kernels (user order).
+hipError_t launch_mix_fwd(const sdn_plan_s &p, const float2 *u, const float2 *V, int K, int k,
+                          float2 *y, int accumulate, hipStream_t st);
+hipError_t launch_mix_adj(const sdn_plan_s &p, const float2 *r, const float2 *V, int K, int k,
+                          float2 *out, hipStream_t st);
+
+}  // namespace sdn

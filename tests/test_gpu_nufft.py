@@ -1,0 +1,153 @@
+"""Plain type-2 / type-1 NUFFT through the C ABI against the FP64 oracle (GPU).
+
+Truth is the direct NUDFT; the FP64 gridding NUFFT with the same kernel,
+width and fine grid is the tighter engineering check of the kernels.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2408_02367_amd as sdn
+import workloads as wl
+from gpu_common import TOL, c64, cimg, host, rel, to_gpu, uniform_points
+from oracle import gridding, nudft
+
+pytestmark = pytest.mark.gpu
+
+
+def _plan(traj, shape, **kw):
+    return sdn.Plan(to_gpu(traj), shape, **kw)
+
+
+def test_c1_type2_and_type1_vs_direct():
+    # 32^3 image, 64^3 fine grid, 8 golden-angle spiral projections x 1024
+    w = wl.make("c1")
+    f = w["x"][0]
+    traj = w["traj"]
+    p = _plan(traj, f.shape)
+    y = host(p.forward(c64(f[None])))[0]
+    ref = nudft.type2(f, traj)
+    assert rel(y, ref) < TOL
+    assert rel(y, gridding.type2(f, traj)) < 5e-6
+    c = wl.random_kspace(traj.shape[0], 11)
+    img = host(p.adjoint(c64(c[None])))[0]
+    ref1 = nudft.type1(c, traj, f.shape)
+    assert rel(img, ref1) < TOL
+    assert rel(img, gridding.type1(c, traj, f.shape)) < 5e-6
+
+
+@pytest.mark.parametrize("shape,M", [((9, 11, 7), 3001), ((12, 10, 14), 4097),
+                                     ((20, 24, 18), 777), ((17, 16, 33), 5000)])
+def test_odd_noncubic_shapes_and_ragged_counts(shape, M):
+    traj = uniform_points(M, sum(shape))
+    f = cimg(shape, M)
+    p = _plan(traj, shape)
+    assert p.info()["fine"] == tuple(gridding.Grid(shape).nf)
+    y = host(p.forward(c64(f[None])))[0]
+    assert rel(y, nudft.type2(f, traj)) < TOL
+    c = cimg((M,), 3)
+    img = host(p.adjoint(c64(c[None])))[0]
+    assert rel(img, nudft.type1(c, traj, shape)) < TOL
+
+
+def test_batch_equals_single_calls():
+    shape = (16, 16, 16)
+    traj = uniform_points(5000, 1)
+    p = _plan(traj, shape)
+    f = cimg((3,) + shape, 2)
+    yb = host(p.forward(c64(f)))
+    for b in range(3):
+        ys = host(p.forward(c64(f[b:b + 1])))[0]
+        assert rel(yb[b], ys) < 1e-6
+        assert rel(yb[b], nudft.type2(f[b], traj)) < TOL
+    c = cimg((3, 5000), 4)
+    ib = host(p.adjoint(c64(c)))
+    for b in range(3):
+        assert rel(ib[b], nudft.type1(c[b], traj, shape)) < TOL
+
+
+def test_adjoint_identity_fp32():
+    shape = (24, 20, 22)
+    traj = uniform_points(20000, 5)
+    p = _plan(traj, shape)
+    f = cimg(shape, 6)
+    c = cimg((20000,), 7)
+    y = host(p.forward(c64(f[None])))[0].astype(np.complex128)
+    g = host(p.adjoint(c64(c[None])))[0].astype(np.complex128)
+    lhs, rhs = np.vdot(c, y), np.vdot(g, f)
+    assert abs(lhs - rhs) / abs(lhs) < 1e-5
+
+
+def test_boundary_and_on_node_coordinates():
+    shape = (8, 8, 8)
+    k = np.array([[0, 0, 0], [-np.pi, 0, 0], [-np.pi, -np.pi, -np.pi], [np.pi / 2, -np.pi / 4, 0],
+                  [3.0, -3.0, 0.5], [np.pi * 0.999999, 0, -np.pi]], dtype=np.float32)
+    f = cimg(shape, 8)
+    p = _plan(k, shape)
+    y = host(p.forward(c64(f[None])))[0]
+    assert rel(y, nudft.type2(f, k)) < TOL
+    assert rel(y, gridding.type2(f, k)) < 5e-6
+
+
+def test_coordinates_outside_pi_fold():
+    shape = (10, 12, 14)
+    k = uniform_points(2000, 9)
+    shift = np.random.default_rng(10).integers(-3, 4, k.shape).astype(np.float32)
+    k2 = (k.astype(np.float64) + 2 * np.pi * shift).astype(np.float32)
+    f = cimg(shape, 11)
+    p = _plan(k2, shape)
+    y = host(p.forward(c64(f[None])))[0]
+    assert rel(y, nudft.type2(f, k2)) < TOL
+
+
+def test_single_point_and_empty_plan():
+    shape = (6, 7, 8)
+    f = cimg(shape, 12)
+    k = np.array([[0.3, -1.2, 2.9]], dtype=np.float32)
+    p = _plan(k, shape)
+    y = host(p.forward(c64(f[None])))[0]
+    assert rel(y, nudft.type2(f, k)) < TOL
+    e = sdn.Plan(torch.zeros(0, 3, device="cuda"), shape)
+    assert e.info()["M"] == 0
+    out = e.adjoint(torch.zeros(1, 0, dtype=torch.complex64, device="cuda"))
+    assert np.all(host(out) == 0)
+    assert e.forward(c64(f[None])).shape == (1, 0)
+
+
+def test_hot_tile_split_and_tile_sizes():
+    # every point in one tile: the tile is split into many work items
+    shape = (16, 16, 16)
+    g = np.random.default_rng(13)
+    k = (g.uniform(-0.05, 0.05, (30000, 3))).astype(np.float32)
+    f = cimg(shape, 14)
+    c = cimg((30000,), 15)
+    ref2 = nudft.type2(f, k)
+    ref1 = nudft.type1(c, k, shape)
+    for tile in (0, 4, 16):
+        p = _plan(k, shape, tile=tile, max_points_per_item=512)
+        assert p.info()["nwork"] >= 30000 // 512
+        assert rel(host(p.forward(c64(f[None])))[0], ref2) < TOL
+        assert rel(host(p.adjoint(c64(c[None])))[0], ref1) < TOL
+
+
+@pytest.mark.parametrize("W,tol", [(4, 2e-3), (8, TOL)])
+def test_other_kernel_widths(W, tol):
+    shape = (14, 14, 14)
+    traj = uniform_points(3000, 16)
+    f = cimg(shape, 17)
+    p = _plan(traj, shape, W=W)
+    y = host(p.forward(c64(f[None])))[0]
+    assert rel(y, nudft.type2(f, traj)) < tol
+    assert rel(y, gridding.Grid(shape, 2.0, W).type2(f, traj)) < 5e-6
+
+
+def test_nonfinite_coordinate_is_a_range_error():
+    k = uniform_points(100, 18)
+    k[37, 1] = np.nan
+    with pytest.raises(sdn.SdnError) as e:
+        _plan(k, (8, 8, 8))
+    assert e.value.status == -2
+    k[37, 1] = np.inf
+    with pytest.raises(sdn.SdnError):
+        _plan(k, (8, 8, 8))

@@ -1,0 +1,227 @@
+"""Benchmark of the StoDIP data-consistency hot path on one MI355X.
+
+A step is one minibatch DC gradient of the MRF subspace operator (forward,
+residual, loss and adjoint; Algorithm 1's forward + loss.backward() for the
+NUFFT part) over the whole-brain-shaped synthetic workload: 160^3 image x
+K = 5 subspace channels, a minibatch of 4 of 32 coils, T = 1000 frames x 8
+spiral interleaves x 1200 samples (M = 9.6M points), W = 6, sigma = 2.
+
+Prints one JSON line: throughput in nonuniform points x channels per second
+(M * B * K per fwd+adj), the plain per-coil/per-channel path beside it, a
+per-stage breakdown from HIP events recorded around every kernel launch of
+the timed steps, the roofline of the dominant kernel and the CPU FP64 oracle
+timed on a bounded sample.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+WORKLOAD = "c4"
+
+
+def _args():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--plain-steps", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 20,
+                    help="points of the CPU oracle sample")
+    return ap.parse_args()
+
+
+def stage_bytes(g):
+    """Algorithmic HBM bytes of one launch of each stage (complex64 = 8 B,
+    point record = 24 B), for the DC-gradient step."""
+    c8 = 8
+    P, B, K, M = g["P"], g["B"], g["K"], g["M"]
+    nvox = g["Nx"] * g["Ny"] * g["Nz"]
+    G = g["nfx"] * g["nfy"] * g["nfz"]
+    xline = g["nfx"] * g["Ny"] * g["Nz"]           # x-transformed image lines
+    xyplane = g["nfx"] * g["nfy"] * g["Nz"]        # xy-transformed image planes
+    return {
+        "pre_fftx": c8 * ((K + B) * nvox + P * xline),
+        "fft_y": c8 * P * (xline + xyplane),
+        "fft_z": c8 * P * (xyplane + G),
+        "interp": c8 * (P * G + 2 * B * M) + 24 * M,
+        "clear": c8 * P * G,
+        "spread": c8 * (P * G + B * M) + 24 * M,
+        "ifft_z": c8 * P * (G + xyplane),
+        "ifft_y": c8 * P * (xyplane + xline),
+        "post_ifftx": c8 * (P * xline + (B + K) * nvox),
+    }
+
+
+def cpu_baseline(w, x, smaps, sample):
+    """The FP64 oracle's gridding fwd+adj for one (coil, channel) pair of the
+    workload: grid stages in full, point stages on a seeded random sample of
+    points, extrapolated linearly to all M points."""
+    from oracle import gridding
+    from oracle.gridding import _WORKERS
+
+    grid = gridding.Grid(w["shape"])
+    M = w["traj"].shape[0]
+    sel = np.sort(np.random.default_rng(7).choice(M, size=min(sample, M), replace=False))
+    pts = w["traj"][sel]
+    f = x[0].astype(np.complex128) * smaps[w["coil_idx"][0]].astype(np.complex128)
+    t0 = time.perf_counter()
+    G = grid.fft(grid.deapodise_pad(f))
+    t1 = time.perf_counter()
+    u = grid.interp(G, pts)
+    t2 = time.perf_counter()
+    H = grid.spread(u, pts)
+    t3 = time.perf_counter()
+    grid.crop_deapodise(grid.ifft(H))
+    t4 = time.perf_counter()
+    t_grid = (t1 - t0) + (t4 - t3)
+    t_pts = (t3 - t1) * (M / len(sel))
+    return {"value": M / (t_grid + t_pts), "unit": "pts*ch/s", "cores": _WORKERS,
+            "kind": "oracle",
+            "sample": f"one (coil, channel) fwd+adj of the 160^3 workload: deapodise/FFT/IFFT/"
+                      f"crop on the full 320^3 grid ({t_grid:.2f} s), interp+spread on "
+                      f"{len(sel)} of {M} points ({t3 - t1:.2f} s) scaled to all points",
+            "seconds": t4 - t0}
+
+
+def _log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def main():
+    a = _args()
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported "
+              "(the coil axis would shard across GPUs, see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2408_02367_amd as sdn
+    import workloads as wl
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    _log("drawing the synthetic workload")
+    w = wl.make(WORKLOAD)
+    shape, K, B = w["shape"], w["K"], w["B"]
+    M = w["traj"].shape[0]
+    x_true = w["x"]
+    # the point of evaluation: 10% RMS smooth perturbation of the truth
+    pert = wl.phantom(shape, K, w["seed"] + 100)
+    pert *= 0.1 * np.sqrt(np.mean(np.abs(x_true) ** 2) / np.mean(np.abs(pert) ** 2))
+    x_np = (x_true + pert).astype(np.complex64)
+
+    _log("building the plan")
+    plan = sdn.Plan(torch.from_numpy(w["traj"]).to(dev), shape,
+                    frame_of_point=torch.from_numpy(w["frame"]).to(dev), T=w["T"])
+    info = plan.info()
+    smaps = torch.from_numpy(w["smaps"]).to(dev)
+    V = torch.from_numpy(w["V"]).to(dev)
+    ci = w["coil_idx"]
+    xt = torch.from_numpy(x_true).to(dev)
+    x = torch.from_numpy(x_np).to(dev)
+    # simulated measurements of the minibatch coils: A x_true + 1% noise
+    y_clean = sdn.mrf_forward(plan, xt, smaps, ci, V)
+    torch.cuda.synchronize()
+    rms = torch.sqrt(torch.mean(torch.abs(y_clean) ** 2, dim=1)).cpu().numpy()
+    noise = wl.complex_noise((B, M), 0.01, rms, w["seed"])
+    d = (y_clean + torch.from_numpy(noise).to(dev)).contiguous()
+    del y_clean, xt
+    grad = torch.empty_like(x)
+    loss = torch.empty(1, dtype=torch.float64, device=dev)
+
+    def step():
+        sdn.mrf_dc_grad(plan, x, smaps, ci, V, d, grad=grad, loss=loss)
+
+    _log("warmup")
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    plan.profile(True)
+    plan.profile_read(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stages = plan.profile_read(reset=True)
+    plan.profile(False)
+    ms_step = (t1 - t0) * 1e3 / a.steps
+    P = B * K
+    value = M * P / (ms_step * 1e-3)
+
+    # the plain per-coil/per-channel path on the same plan and data
+    yp = torch.empty_like(d)
+    xo = torch.empty_like(x)
+
+    def plain_step():
+        sdn.mrf_forward(plan, x, smaps, ci, V, out=yp, plain=True)
+        sdn.mrf_adjoint(plan, d, smaps, ci, V, out=xo, plain=True)
+
+    _log(f"batched: {ms_step:.3f} ms/step; timing the plain path")
+    plain_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.plain_steps):
+        _log(f"batched: {ms_step:.3f} ms/step; timing the plain path")
+    plain_step()
+    torch.cuda.synchronize()
+    plain_ms = (time.perf_counter() - t0) * 1e3 / a.plain_steps
+
+    geo = dict(P=P, B=B, K=K, M=M, Nz=shape[0], Ny=shape[1], Nx=shape[2],
+               nfz=info["fine"][0], nfy=info["fine"][1], nfx=info["fine"][2])
+    sb = stage_bytes(geo)
+    per_stage = {}
+    for s, (ms, n) in stages.items():
+        avg = ms / n
+        per_stage[s] = {"ms_per_step": round(ms / a.steps, 4), "launches": n,
+                        "avg_launch_ms": round(avg, 4)}
+        if s in sb:
+            per_stage[s]["algo_GBps"] = round(sb[s] / (avg * 1e-3) / 1e9, 1)
+    dom = max((s for s in stages if s in sb), key=lambda s: stages[s][0])
+    dom_avg_s = stages[dom][0] / stages[dom][1] * 1e-3
+    achieved = sb[dom] / dom_avg_s / 1e9
+    roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0,
+                "unit": "GB/s", "frac": round(achieved / 8000.0, 4), "traffic": None,
+                "algo_bytes_per_launch": sb[dom]}
+
+    out = {
+        "metric": "NUFFT fwd+adj nonuniform pts*ch/s (minibatch DC gradient)",
+        "value": round(value, 1),
+        "unit": "pts*ch/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32",
+        "data": "synthetic",
+        "config": {"workload": "160^3 x K=5 subspace image, 4-of-32 coil minibatch, "
+                               "T=1000 frames x 8 spiral interleaves x 1200 samples "
+                               "(M=9.6M), KB W=6, sigma=2 (320^3 grid): batched DC gradient",
+                   "shape": list(shape), "K": K, "B": B, "C": w["C"], "M": M, "T": w["T"],
+                   "W": info["W"], "sigma": info["sigma"]},
+        "plain_ms_per_step": round(plain_ms, 3),
+        "speedup_vs_plain": round(plain_ms / ms_step, 3),
+        "stages": per_stage,
+        "roofline": roofline,
+        "torch_peak_mem_GB": round(torch.cuda.max_memory_allocated() / 1e9, 2),
+        "plan_workspace_GB": round(plan.workspace_size(B, K) / 1e9, 2),
+    }
+    _log(f"plain: {plain_ms:.3f} ms/step")
+    if not a.no_cpu_baseline:
+        _log("timing the CPU oracle sample")
+        out["cpu_baseline"] = cpu_baseline(w, w["x"], w["smaps"], a.cpu_sample)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

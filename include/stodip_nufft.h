@@ -62,8 +62,10 @@ typedef enum {
 typedef struct {
   int W;                   /* kernel width in fine-grid cells: 4, 6 or 8 (default 6) */
   double sigma;            /* oversampling ratio, 1.25 <= sigma <= 4 (default 2.0)   */
-  int tile;                /* bin / tile edge in fine cells; 0 = library choice       */
-  int max_points_per_item; /* cap on points per spreading work item; 0 = library     */
+  int tile;                /* tile edge in fine cells, 4..32 on every axis;
+                              0 = library choice (16 x 16 x 8)                      */
+  int max_points_per_item; /* cap on points per interpolation work item, <= 2048;
+                              0 = library choice (2048)                              */
   size_t workspace_budget; /* bytes of fine-grid workspace; 0 = unlimited.  Calls
                               whose coil minibatch does not fit run coil-chunked.   */
 } sdn_opts;
@@ -76,11 +78,12 @@ typedef struct {
   int32_t T;               /* frames (rows of V)                                    */
   int W;
   double sigma, beta;      /* Kaiser-Bessel shape parameter                          */
-  int64_t tile[3];         /* (bz, by, bx)                                          */
+  int64_t tile[3];         /* (bz, by, bx) tile edges in fine cells                  */
   int64_t nbins;           /* tiles of the fine grid                                */
-  int64_t nwork;           /* spreading work items (hot tiles split)                 */
+  int64_t nwork;           /* interpolation work items (crowded tiles split)        */
   int64_t max_bin;         /* points in the most populated tile                      */
   int ncoef;               /* coefficients per piece of the kernel polynomial        */
+  int64_t nvisit;          /* (point, tile) pairs of the spreading lists             */
 } sdn_plan_info;
 
 /* Library defaults: W = 6, sigma = 2, automatic tiles, no budget. */
@@ -178,6 +181,30 @@ SDN_API sdn_status sdn_workspace_size(sdn_plan plan, int B, int K, size_t *bytes
 
 /* Release the plan's cached workspace (it is re-allocated on demand). */
 SDN_API sdn_status sdn_release_workspace(sdn_plan plan);
+
+/* Stages of the operator, for per-stage timing. */
+typedef enum {
+  SDN_STAGE_PRE_FFTX = 0,   /* coil multiply + deapodise + pad + x FFT     */
+  SDN_STAGE_FFT_Y = 1,      /* forward y FFT pass                          */
+  SDN_STAGE_FFT_Z = 2,      /* forward z FFT pass                          */
+  SDN_STAGE_INTERP = 3,     /* interpolation + subspace mix (+ residual)   */
+  SDN_STAGE_CLEAR = 4,      /* fine-grid clear before spreading            */
+  SDN_STAGE_SPREAD = 5,     /* spreading with the conjugate subspace mix   */
+  SDN_STAGE_IFFT_Z = 6,     /* adjoint z FFT pass                          */
+  SDN_STAGE_IFFT_Y = 7,     /* adjoint y FFT pass                          */
+  SDN_STAGE_POST_IFFTX = 8, /* x IFFT + crop + deapodise + conj coil sum   */
+  SDN_STAGE_MIX = 9,        /* separate subspace-mix kernels (plain path)  */
+  SDN_NUM_STAGES = 10
+} sdn_stage;
+
+/*
+ * Per-stage timing with HIP events recorded on the caller's stream around
+ * every kernel launch of the plan while enabled.  sdn_profile_read waits for
+ * the recorded events and returns, per stage, the summed kernel time in ms
+ * and the number of launches since the last reset.
+ */
+SDN_API sdn_status sdn_profile_enable(sdn_plan plan, int enable);
+SDN_API sdn_status sdn_profile_read(sdn_plan plan, double *ms, int64_t *launches, int reset);
 
 /*
  * Host-only view of the kernel tables a plan would use (no device work):

@@ -32,7 +32,9 @@ import scipy.fft
 from . import kernel
 from .nudft import modes
 
-_WORKERS = max(1, len(os.sched_getaffinity(0)))
+# FFT threads: the cores this process may use, capped by OMP_NUM_THREADS
+_WORKERS = max(1, min(len(os.sched_getaffinity(0)),
+                      int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or 1 << 30))
 
 
 class Grid:

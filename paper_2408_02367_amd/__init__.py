@@ -32,7 +32,12 @@ _STATUS = {0: "SDN_OK", -1: "SDN_E_INVALID", -2: "SDN_E_RANGE", -3: "SDN_E_NOMEM
 API = ["sdn_default_opts", "sdn_plan_create", "sdn_plan_destroy", "sdn_plan_get_info",
        "sdn_forward", "sdn_adjoint", "sdn_mrf_forward", "sdn_mrf_adjoint", "sdn_mrf_dc_grad",
        "sdn_mrf_forward_plain", "sdn_mrf_adjoint_plain", "sdn_workspace_size",
-       "sdn_release_workspace", "sdn_kernel_tables", "sdn_last_error"]
+       "sdn_release_workspace", "sdn_profile_enable", "sdn_profile_read",
+       "sdn_kernel_tables", "sdn_last_error"]
+
+# stage names, in the order of the sdn_stage enum
+STAGES = ["pre_fftx", "fft_y", "fft_z", "interp", "clear", "spread", "ifft_z", "ifft_y",
+          "post_ifftx", "mix"]
 
 
 class SdnError(RuntimeError):
@@ -51,7 +56,8 @@ class PlanInfo(ctypes.Structure):
                 ("M", ctypes.c_int64), ("T", ctypes.c_int32), ("W", ctypes.c_int),
                 ("sigma", ctypes.c_double), ("beta", ctypes.c_double),
                 ("tile", ctypes.c_int64 * 3), ("nbins", ctypes.c_int64),
-                ("nwork", ctypes.c_int64), ("max_bin", ctypes.c_int64), ("ncoef", ctypes.c_int)]
+                ("nwork", ctypes.c_int64), ("max_bin", ctypes.c_int64), ("ncoef", ctypes.c_int),
+                ("nvisit", ctypes.c_int64)]
 
 
 _lib = None
@@ -82,6 +88,8 @@ def lib():
         L.sdn_mrf_dc_grad.argtypes = mrf + [vp, vp, vp, vp]
         L.sdn_workspace_size.argtypes = [vp, i32, i32, ctypes.POINTER(ctypes.c_size_t)]
         L.sdn_release_workspace.argtypes = [vp]
+        L.sdn_profile_enable.argtypes = [vp, i32]
+        L.sdn_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), i32]
         L.sdn_kernel_tables.argtypes = [i32, ctypes.c_double, i64, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(i32), ctypes.POINTER(i32),
                                         ctypes.POINTER(ctypes.c_float),
@@ -179,12 +187,23 @@ class Plan:
         _check(lib().sdn_plan_get_info(self.handle, ctypes.byref(i)))
         return dict(shape=tuple(i.shape), fine=tuple(i.fine), M=i.M, T=i.T, W=i.W,
                     sigma=i.sigma, beta=i.beta, tile=tuple(i.tile), nbins=i.nbins,
-                    nwork=i.nwork, max_bin=i.max_bin, ncoef=i.ncoef)
+                    nwork=i.nwork, max_bin=i.max_bin, ncoef=i.ncoef, nvisit=i.nvisit)
 
     def workspace_size(self, B, K):
         n = ctypes.c_size_t()
         _check(lib().sdn_workspace_size(self.handle, int(B), int(K), ctypes.byref(n)))
         return n.value
+
+    def profile(self, enable=True):
+        """Record HIP events around every kernel launch of this plan."""
+        _check(lib().sdn_profile_enable(self.handle, 1 if enable else 0))
+
+    def profile_read(self, reset=True):
+        """{stage: (summed kernel ms, launches)} since the last reset."""
+        ms = (ctypes.c_double * len(STAGES))()
+        n = (ctypes.c_int64 * len(STAGES))()
+        _check(lib().sdn_profile_read(self.handle, ms, n, 1 if reset else 0))
+        return {s: (ms[i], n[i]) for i, s in enumerate(STAGES) if n[i]}
 
     def release_workspace(self):
         _check(lib().sdn_release_workspace(self.handle))

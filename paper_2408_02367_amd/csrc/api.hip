@@ -54,6 +54,18 @@ sdn_status ensure_kbuf(sdn_plan_s *p, size_t elems) {
   return s;
 }
 
+sdn_status ensure_part(sdn_plan_s *p, int groups, int K) {
+  const size_t elems = spread_part_elems(*p, groups, K);
+  if (p->part_cap >= elems) return SDN_OK;
+  if (p->part) (void)hipFree(p->part);
+  p->part = nullptr;
+  p->part_cap = 0;
+  sdn_status s = hip_check(hipMalloc((void **)&p->part, elems * sizeof(float2)),
+                           "spreading partials");
+  if (s == SDN_OK) p->part_cap = elems;
+  return s;
+}
+
 // Channels of P-channel grids that fit the workspace budget at once.
 sdn_status channels_per_pass(const sdn_plan_s &p, int unit, int units, int *per,
                              const char *fn) {
@@ -75,6 +87,34 @@ sdn_status channels_per_pass(const sdn_plan_s &p, int unit, int units, int *per,
     if (_s != SDN_OK) return _s;           \
   } while (0)
 #define SDN_HIP(expr, what) SDN_TRY(hip_check((expr), what))
+
+hipEvent_t pooled_event(sdn_plan_s *p) {
+  if (!p->ev_pool.empty()) {
+    hipEvent_t e = p->ev_pool.back();
+    p->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Launch one stage; while profiling, bracket it with events on `st`.
+#define SDN_STAGE(p, stage, expr, what)                                         \
+  do {                                                                          \
+    hipEvent_t _e0 = (p)->prof ? pooled_event(p) : nullptr;                     \
+    if (_e0) (void)hipEventRecord(_e0, st);                                     \
+    SDN_HIP((expr), what);                                                      \
+    if (_e0) {                                                                  \
+      hipEvent_t _e1 = pooled_event(p);                                         \
+      if (_e1) {                                                                \
+        (void)hipEventRecord(_e1, st);                                          \
+        (p)->prof_ev.push_back({(stage), _e0, _e1});                            \
+      } else {                                                                  \
+        (p)->ev_pool.push_back(_e0);                                            \
+      }                                                                         \
+    }                                                                           \
+  } while (0)
 
 sdn_status check_mrf_args(const sdn_plan_s &p, const char *fn, const void *x, int K,
                           const void *smaps, int C, const int32_t *coil_idx, int B,
@@ -103,9 +143,9 @@ CoilList coil_list(const int32_t *idx, int b0, int n) {
 sdn_status forward_grid(sdn_plan_s *p, const float2 *x, int K, const float2 *smaps,
                         const CoilList &coils, int B, hipStream_t st) {
   const int P = B * K;
-  SDN_HIP(launch_pre_fftx(*p, x, K, smaps, coils, B, p->grid, st), "forward x pass");
-  SDN_HIP(launch_fft_axis(*p, p->grid, P, 1, false, true, false, st), "forward y pass");
-  SDN_HIP(launch_fft_axis(*p, p->grid, P, 2, false, true, false, st), "forward z pass");
+  SDN_STAGE(p, SDN_STAGE_PRE_FFTX, launch_pre_fftx(*p, x, K, smaps, coils, B, p->grid, st), "forward x pass");
+  SDN_STAGE(p, SDN_STAGE_FFT_Y, launch_fft_axis(*p, p->grid, P, 1, false, true, false, st), "forward y pass");
+  SDN_STAGE(p, SDN_STAGE_FFT_Z, launch_fft_axis(*p, p->grid, P, 2, false, true, false, st), "forward z pass");
   return SDN_OK;
 }
 
@@ -113,10 +153,11 @@ sdn_status forward_grid(sdn_plan_s *p, const float2 *x, int K, const float2 *sma
 sdn_status adjoint_grid(sdn_plan_s *p, int K, const float2 *smaps, const CoilList &coils, int B,
                         float2 *xout, int accumulate, hipStream_t st) {
   const int P = B * K;
-  SDN_HIP(launch_fft_axis(*p, p->grid, P, 2, true, false, true, st), "adjoint z pass");
-  SDN_HIP(launch_fft_axis(*p, p->grid, P, 1, true, false, true, st), "adjoint y pass");
-  SDN_HIP(launch_post_ifftx(*p, p->grid, K, smaps, coils, B, xout, accumulate, st),
-          "adjoint x pass");
+  SDN_STAGE(p, SDN_STAGE_IFFT_Z, launch_fft_axis(*p, p->grid, P, 2, true, false, true, st), "adjoint z pass");
+  SDN_STAGE(p, SDN_STAGE_IFFT_Y, launch_fft_axis(*p, p->grid, P, 1, true, false, true, st), "adjoint y pass");
+  SDN_STAGE(p, SDN_STAGE_POST_IFFTX,
+            launch_post_ifftx(*p, p->grid, K, smaps, coils, B, xout, accumulate, st),
+            "adjoint x pass");
   return SDN_OK;
 }
 
@@ -159,7 +200,7 @@ sdn_status sdn_forward(sdn_plan p, const void *img, void *ksp, int batch, void *
     a.groups = pc;
     a.kg = 1;
     a.y = (float2 *)ksp + (size_t)c0 * p->M;
-    SDN_HIP(launch_interp(*p, a, st), "interpolation");
+    SDN_STAGE(p, SDN_STAGE_INTERP, launch_interp(*p, a, st), "interpolation");
   }
   return SDN_OK;
 }
@@ -181,15 +222,16 @@ sdn_status sdn_adjoint(sdn_plan p, const void *ksp, void *img, int batch, void *
     const int pc = std::min(per, batch - c0);
     const size_t cells = (size_t)pc * fine_cells(*p);
     SDN_TRY(ensure_grid(p, cells));
-    SDN_HIP(launch_fill_zero(p->grid, cells, st), "grid clear");
+    SDN_TRY(ensure_part(p, pc, 1));
     SpreadArgs s{};
     s.grid = p->grid;
-    s.P = pc;
+    s.part = p->part;
+    s.groups = pc;
     s.K = 1;
     s.V = nullptr;
     s.src = (const float2 *)ksp + (size_t)c0 * p->M;
     s.src_plan_order = false;
-    SDN_HIP(launch_spread(*p, s, st), "spreading");
+    SDN_STAGE(p, SDN_STAGE_SPREAD, launch_spread(*p, s, st), "spreading");
     SDN_TRY(adjoint_grid(p, pc, nullptr, one, 1, (float2 *)img + c0 * nvox, 0, st));
   }
   return SDN_OK;
@@ -216,7 +258,7 @@ sdn_status sdn_mrf_forward(sdn_plan p, const void *x, int K, const void *smaps, 
     a.kg = K;
     a.V = (const float2 *)V;
     a.y = (float2 *)y + (size_t)b0 * p->M;
-    SDN_HIP(launch_interp(*p, a, st), "interpolation");
+    SDN_STAGE(p, SDN_STAGE_INTERP, launch_interp(*p, a, st), "interpolation");
   }
   return SDN_OK;
 }
@@ -238,15 +280,16 @@ sdn_status sdn_mrf_adjoint(sdn_plan p, const void *y, int K, const void *smaps, 
     const CoilList coils = coil_list(coil_idx, b0, bc);
     const size_t cells = (size_t)bc * K * fine_cells(*p);
     SDN_TRY(ensure_grid(p, cells));
-    SDN_HIP(launch_fill_zero(p->grid, cells, st), "grid clear");
+    SDN_TRY(ensure_part(p, bc, K));
     SpreadArgs s{};
     s.grid = p->grid;
-    s.P = bc * K;
+    s.part = p->part;
+    s.groups = bc;
     s.K = K;
     s.V = (const float2 *)V;
     s.src = (const float2 *)y + (size_t)b0 * p->M;
     s.src_plan_order = false;
-    SDN_HIP(launch_spread(*p, s, st), "spreading");
+    SDN_STAGE(p, SDN_STAGE_SPREAD, launch_spread(*p, s, st), "spreading");
     SDN_TRY(adjoint_grid(p, K, (const float2 *)smaps, coils, bc, (float2 *)x_out,
                          (accumulate || b0 > 0) ? 1 : 0, st));
   }
@@ -281,16 +324,17 @@ sdn_status sdn_mrf_dc_grad(sdn_plan p, const void *x, int K, const void *smaps, 
     a.w = w;
     a.r_plan = p->kbuf;
     a.loss = loss;
-    SDN_HIP(launch_interp(*p, a, st), "interpolation + residual");
-    SDN_HIP(launch_fill_zero(p->grid, cells, st), "grid clear");
+    SDN_STAGE(p, SDN_STAGE_INTERP, launch_interp(*p, a, st), "interpolation + residual");
+    SDN_TRY(ensure_part(p, bc, K));
     SpreadArgs s{};
     s.grid = p->grid;
-    s.P = bc * K;
+    s.part = p->part;
+    s.groups = bc;
     s.K = K;
     s.V = (const float2 *)V;
     s.src = p->kbuf;
     s.src_plan_order = true;
-    SDN_HIP(launch_spread(*p, s, st), "spreading");
+    SDN_STAGE(p, SDN_STAGE_SPREAD, launch_spread(*p, s, st), "spreading");
     SDN_TRY(adjoint_grid(p, K, (const float2 *)smaps, coils, bc, (float2 *)grad, b0 > 0 ? 1 : 0,
                          st));
   }
@@ -317,10 +361,9 @@ sdn_status sdn_mrf_forward_plain(sdn_plan p, const void *x, int K, const void *s
       a.groups = 1;
       a.kg = 1;
       a.y = p->kbuf;
-      SDN_HIP(launch_interp(*p, a, st), "interpolation");
-      SDN_HIP(launch_mix_fwd(*p, p->kbuf, (const float2 *)V, K, k, (float2 *)y + (size_t)b * p->M,
-                             k > 0 ? 1 : 0, st),
-              "subspace mix");
+      SDN_STAGE(p, SDN_STAGE_INTERP, launch_interp(*p, a, st), "interpolation");
+      SDN_STAGE(p, SDN_STAGE_MIX, launch_mix_fwd(*p, p->kbuf, (const float2 *)V, K, k, (float2 *)y + (size_t)b * p->M,
+                             k > 0 ? 1 : 0, st), "subspace mix");
     }
   }
   return SDN_OK;
@@ -342,18 +385,18 @@ sdn_status sdn_mrf_adjoint_plain(sdn_plan p, const void *y, int K, const void *s
   for (int b = 0; b < B; ++b) {
     const CoilList coil = coil_list(coil_idx, b, 1);
     for (int k = 0; k < K; ++k) {
-      SDN_HIP(launch_mix_adj(*p, (const float2 *)y + (size_t)b * p->M, (const float2 *)V, K, k,
-                             p->kbuf, st),
-              "subspace mix");
-      SDN_HIP(launch_fill_zero(p->grid, fine_cells(*p), st), "grid clear");
+      SDN_STAGE(p, SDN_STAGE_MIX, launch_mix_adj(*p, (const float2 *)y + (size_t)b * p->M, (const float2 *)V, K, k,
+                             p->kbuf, st), "subspace mix");
+      SDN_TRY(ensure_part(p, 1, 1));
       SpreadArgs s{};
       s.grid = p->grid;
-      s.P = 1;
+      s.part = p->part;
+      s.groups = 1;
       s.K = 1;
       s.V = nullptr;
       s.src = p->kbuf;
       s.src_plan_order = false;
-      SDN_HIP(launch_spread(*p, s, st), "spreading");
+      SDN_STAGE(p, SDN_STAGE_SPREAD, launch_spread(*p, s, st), "spreading");
       SDN_TRY(adjoint_grid(p, 1, (const float2 *)smaps, coil, 1, (float2 *)x_out + k * nvox,
                            (accumulate || b > 0) ? 1 : 0, st));
     }
@@ -370,13 +413,44 @@ sdn_status sdn_workspace_size(sdn_plan p, int B, int K, size_t *bytes) {
   return SDN_OK;
 }
 
+sdn_status sdn_profile_enable(sdn_plan p, int enable) {
+  SDN_TRY(check_plan(p, "sdn_profile_enable"));
+  p->prof = enable ? 1 : 0;
+  return SDN_OK;
+}
+
+sdn_status sdn_profile_read(sdn_plan p, double *ms, int64_t *launches, int reset) {
+  SDN_TRY(check_plan(p, "sdn_profile_read"));
+  for (auto &r : p->prof_ev) {
+    SDN_HIP(hipEventSynchronize(r.stop), "profile event wait");
+    float t = 0.f;
+    SDN_HIP(hipEventElapsedTime(&t, r.start, r.stop), "profile event time");
+    p->prof_ms[r.stage] += t;
+    p->prof_n[r.stage] += 1;
+    p->ev_pool.push_back(r.start);
+    p->ev_pool.push_back(r.stop);
+  }
+  p->prof_ev.clear();
+  for (int i = 0; i < SDN_NUM_STAGES; ++i) {
+    if (ms) ms[i] = p->prof_ms[i];
+    if (launches) launches[i] = p->prof_n[i];
+    if (reset) {
+      p->prof_ms[i] = 0.0;
+      p->prof_n[i] = 0;
+    }
+  }
+  return SDN_OK;
+}
+
 sdn_status sdn_release_workspace(sdn_plan p) {
   SDN_TRY(check_plan(p, "sdn_release_workspace"));
   if (p->grid) (void)hipFree(p->grid);
   if (p->kbuf) (void)hipFree(p->kbuf);
+  if (p->part) (void)hipFree(p->part);
   p->grid = nullptr;
   p->kbuf = nullptr;
-  p->grid_cap = p->kbuf_cap = 0;
+  p->part = nullptr;
+  p->grid_cap = p->kbuf_cap = p->part_cap = 0;
   return SDN_OK;
 }
 

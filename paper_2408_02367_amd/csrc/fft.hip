@@ -1,5 +1,5 @@
 // The sigma-oversampled 3D FFT of the gridding NUFFT, as three LDS-staged
-// line passes over a fine grid stored [z][y][x][p] (P channels innermost).
+// line passes over P channel-major fine grids stored [p][z][y][x].
 //
 // Forward (image -> fine grid spectrum):
 //   x pass: fused with the coil multiply, deapodisation and zero padding -
@@ -44,77 +44,73 @@ struct PreArgs {
   const float2 *smaps;  // [C][Nz][Ny][Nx] or null
   CoilList coils;
   int K, P;             // P = B K, channel p = b K + k
-  int Pc, NL;           // channels and lines per workgroup
-  float2 *grid;         // [nfz][nfy][nfx][P]
+  int NL;               // lines (columns) per workgroup
+  int S;                // LDS row stride (>= NL, odd)
+  float2 *grid;         // [P][nfz][nfy][nfx]
   const float *dx, *dy, *dz;
   const float2 *tw;
   RadixPlan rp;
   LineGeom g;
 };
 
+// One workgroup transforms NL x-lines; line n = (z Ny + y) P + p, so the
+// lines of one workgroup share (z, y) and reuse the image and coil rows.
 __global__ void __launch_bounds__(kFftThreads)
 k_pre_fftx(PreArgs a) {
   extern __shared__ float2 smem[];
   const LineGeom &g = a.g;
-  const int L = g.nfx;
-  const int C = a.NL * a.Pc;
+  const int L = g.nfx, C = a.NL, S = a.S;
   float2 *lds = smem;
-  float2 *tw = smem + L * C;
+  float2 *tw = smem + L * S;
   const int tid = threadIdx.x;
-  const int line0 = blockIdx.x * a.NL;
-  const int p0 = blockIdx.y * a.Pc;
-  const int nlines = g.Nz * g.Ny;
+  const int line0 = blockIdx.x * C;
+  const int nlines = g.Nz * g.Ny * a.P;
+  const size_t nvox = (size_t)g.Nz * g.Ny * g.Nx;
   for (int m = tid; m < L; m += kFftThreads) tw[m] = a.tw[m];
-  // zero the padding rows
+  // zero the padding rows [N - half, nf - half)
   const int nzero = (L - g.Nx) * C;
   for (int e = tid; e < nzero; e += kFftThreads) {
     const int c = e % C, r = e / C;
-    const int l = (g.Nx - g.hx) + r;   // rows [N - half, nf - half) are padding
-    lds[l * C + c] = make_float2(0.f, 0.f);
+    lds[((g.Nx - g.hx) + r) * S + c] = make_float2(0.f, 0.f);
   }
   // coil * image / deapodisation, placed at fine positions
-  const int nload = a.NL * a.Pc * g.Nx;
-  for (int e = tid; e < nload; e += kFftThreads) {
-    const int xq = e % g.Nx;
-    const int rest = e / g.Nx;
-    const int pp = rest % a.Pc, ls = rest / a.Pc;
-    const int line = line0 + ls, p = p0 + pp;
+  for (int e = tid; e < C * g.Nx; e += kFftThreads) {
+    const int xq = e % g.Nx, c = e / g.Nx;
+    const int line = line0 + c;
     float2 v = make_float2(0.f, 0.f);
-    if (line < nlines && p < a.P) {
-      const int z = line / g.Ny, y = line % g.Ny;
+    if (line < nlines) {
+      const int p = line % a.P, zy = line / a.P;
+      const int z = zy / g.Ny, y = zy % g.Ny;
       const int b = p / a.K, k = p % a.K;
-      const size_t vox = ((size_t)z * g.Ny + y) * g.Nx + xq;
-      const size_t nvox = (size_t)g.Nz * g.Ny * g.Nx;
+      const size_t vox = (size_t)zy * g.Nx + xq;
       v = a.x[(size_t)k * nvox + vox];
       if (a.smaps) v = cmul(a.smaps[(size_t)a.coils.idx[b] * nvox + vox], v);
       const float s = a.dx[xq] * a.dy[y] * a.dz[z];
       v.x *= s;
       v.y *= s;
     }
-    lds[fine_pos(xq, g.hx, L) * C + ls * a.Pc + pp] = v;
+    lds[fine_pos(xq, g.hx, L) * S + c] = v;
   }
   __syncthreads();
-  fft_lds<false>(lds, L, C, a.rp, tw);
-  // write the transformed lines
-  const int nst = a.NL * L * a.Pc;
-  for (int e = tid; e < nst; e += kFftThreads) {
-    const int pp = e % a.Pc;
-    const int rest = e / a.Pc;
-    const int l = rest % L, ls = rest / L;
-    const int line = line0 + ls, p = p0 + pp;
-    if (line >= nlines || p >= a.P) continue;
-    const int z = line / g.Ny, y = line % g.Ny;
+  fft_lds<false>(lds, L, C, S, a.rp, tw);
+  for (int e = tid; e < C * L; e += kFftThreads) {
+    const int l = e % L, c = e / L;
+    const int line = line0 + c;
+    if (line >= nlines) continue;
+    const int p = line % a.P, zy = line / a.P;
+    const int z = zy / g.Ny, y = zy % g.Ny;
     const size_t zf = fine_pos(z, g.hz, g.nfz), yf = fine_pos(y, g.hy, g.nfy);
-    a.grid[((zf * g.nfy + yf) * L + l) * a.P + p] = lds[l * C + ls * a.Pc + pp];
+    a.grid[(((size_t)p * g.nfz + zf) * g.nfy + yf) * L + l] = lds[l * S + c];
   }
 }
 
 struct PostArgs {
-  const float2 *grid;   // [nfz][nfy][nfx][P]
+  const float2 *grid;   // [P][nfz][nfy][nfx]
   const float2 *smaps;  // [C][Nz][Ny][Nx] or null
   CoilList coils;
   int K, B, P;
-  int Bc, NL;           // coils per chunk, lines per workgroup
+  int Bc, NL;           // coils per chunk, (z, y) lines per workgroup
+  int S;                // LDS row stride
   float2 *xout;         // [K][Nz][Ny][Nx]
   int accumulate;
   const float *dx, *dy, *dz;
@@ -123,15 +119,18 @@ struct PostArgs {
   LineGeom g;
 };
 
+// One workgroup: NL (z, y) image lines, all channels of Bc coils at a time
+// (column c = line slot * Bc K + b K + k), so the sum over coils stays in
+// the workgroup.
 __global__ void __launch_bounds__(kFftThreads)
 k_post_ifftx(PostArgs a) {
   extern __shared__ float2 smem[];
   const LineGeom &g = a.g;
   const int L = g.nfx;
   const int Pc = a.Bc * a.K;
-  const int C = a.NL * Pc;
+  const int C = a.NL * Pc, S = a.S;
   float2 *lds = smem;
-  float2 *tw = smem + L * C;
+  float2 *tw = smem + L * S;
   const int tid = threadIdx.x;
   const int line0 = blockIdx.x * a.NL;
   const int nlines = g.Nz * g.Ny;
@@ -139,22 +138,20 @@ k_post_ifftx(PostArgs a) {
   for (int m = tid; m < L; m += kFftThreads) tw[m] = a.tw[m];
   for (int b0 = 0; b0 < a.B; b0 += a.Bc) {
     const int p0 = b0 * a.K;
-    const int nld = a.NL * L * Pc;
-    for (int e = tid; e < nld; e += kFftThreads) {
-      const int pp = e % Pc;
-      const int rest = e / Pc;
-      const int l = rest % L, ls = rest / L;
+    for (int e = tid; e < C * L; e += kFftThreads) {
+      const int l = e % L, c = e / L;
+      const int ls = c / Pc, pp = c % Pc;
       const int line = line0 + ls, p = p0 + pp;
       float2 v = make_float2(0.f, 0.f);
       if (line < nlines && p < a.P) {
         const int z = line / g.Ny, y = line % g.Ny;
         const size_t zf = fine_pos(z, g.hz, g.nfz), yf = fine_pos(y, g.hy, g.nfy);
-        v = a.grid[((zf * g.nfy + yf) * L + l) * a.P + p];
+        v = a.grid[(((size_t)p * g.nfz + zf) * g.nfy + yf) * L + l];
       }
-      lds[l * C + ls * Pc + pp] = v;
+      lds[l * S + c] = v;
     }
     __syncthreads();
-    fft_lds<true>(lds, L, C, a.rp, tw);
+    fft_lds<true>(lds, L, C, S, a.rp, tw);
     const int nout = a.NL * a.K * g.Nx;
     for (int e = tid; e < nout; e += kFftThreads) {
       const int xq = e % g.Nx;
@@ -167,10 +164,10 @@ k_post_ifftx(PostArgs a) {
       const int l = fine_pos(xq, g.hx, L);
       float2 acc = make_float2(0.f, 0.f);
       for (int bb = 0; bb < a.Bc && b0 + bb < a.B; ++bb) {
-        const float2 h = lds[l * C + ls * Pc + bb * a.K + k];
+        const float2 h = lds[l * S + ls * Pc + bb * a.K + k];
         if (a.smaps) {
-          const float2 s = a.smaps[(size_t)a.coils.idx[b0 + bb] * nvox + vox];
-          acc = cadd(acc, cmulc(h, s));   // conj(S) * h
+          const float2 sv = a.smaps[(size_t)a.coils.idx[b0 + bb] * nvox + vox];
+          acc = cadd(acc, cmulc(h, sv));   // conj(S) * h
         } else {
           acc = cadd(acc, h);
         }
@@ -191,8 +188,9 @@ struct AxisArgs {
   int L;
   int64_t I;            // contiguous inner extent (columns)
   int C;                // columns per workgroup
-  int64_t so;           // elements between outer slabs
-  int o_lo, o_gap;      // outer o -> slab o < o_lo ? o : o + o_gap
+  int O2;               // outer = (o1 channel, o2 plane): o = o1 * O2 + o2
+  int64_t so1, so2;     // element strides of o1 and of a plane
+  int o_lo, o_gap;      // plane o2 -> o2 < o_lo ? o2 : o2 + o_gap
   int in_lo, in_gap;    // rows [in_lo, in_lo + in_gap) are known zeros
   int Lout, out_lo, out_gap;   // rows written: q -> q < out_lo ? q : q + out_gap
   const float2 *tw;
@@ -209,8 +207,9 @@ k_fft_axis(AxisArgs a) {
   const int tid = threadIdx.x;
   const int64_t c0 = (int64_t)blockIdx.x * C;
   const int o = blockIdx.y;
-  const int64_t slab = o < a.o_lo ? o : o + a.o_gap;
-  float2 *base = a.data + slab * a.so + c0;
+  const int o1 = o / a.O2, o2 = o - o1 * a.O2;
+  const int64_t plane = o2 < a.o_lo ? o2 : o2 + a.o_gap;
+  float2 *base = a.data + o1 * a.so1 + plane * a.so2 + c0;
   for (int m = tid; m < L; m += kFftThreads) tw[m] = a.tw[m];
   for (int e = tid; e < L * C; e += kFftThreads) {
     const int c = e % C, l = e / C;
@@ -219,11 +218,178 @@ k_fft_axis(AxisArgs a) {
     lds[l * C + c] = v;
   }
   __syncthreads();
-  fft_lds<INV>(lds, L, C, a.rp, tw);
+  fft_lds<INV>(lds, L, C, C, a.rp, tw);
   for (int e = tid; e < a.Lout * C; e += kFftThreads) {
     const int c = e % C, q = e / C;
     const int l = q < a.out_lo ? q : q + a.out_gap;
     base[(int64_t)l * a.I + c] = lds[l * C + c];
+  }
+}
+
+// Specialised strided pass: L and C = 16 columns known at compile time.
+template <bool INV, int L>
+__global__ void __launch_bounds__(kFftThreads)
+k_fft_axis_ct(AxisArgs a) {
+  constexpr int C = 16;
+  __shared__ float2 lds[L * C];
+  __shared__ float2 tw[L];
+  const int tid = threadIdx.x;
+  const int64_t c0 = (int64_t)blockIdx.x * C;
+  const int o = blockIdx.y;
+  const int o1 = o / a.O2, o2 = o - o1 * a.O2;
+  const int64_t plane = o2 < a.o_lo ? o2 : o2 + a.o_gap;
+  float2 *base = a.data + o1 * a.so1 + plane * a.so2 + c0;
+  for (int m = tid; m < L; m += kFftThreads) tw[m] = a.tw[m];
+  constexpr int NE = L * C / kFftThreads;   // L * C is a multiple of 256 for every specialisation
+  float2 v[NE];
+#pragma unroll
+  for (int q = 0; q < NE; ++q) {
+    const int e = tid + q * kFftThreads;
+    const int c = e % C, l = e / C;
+    v[q] = (l < a.in_lo || l >= a.in_lo + a.in_gap) ? base[(int64_t)l * a.I + c]
+                                                    : make_float2(0.f, 0.f);
+  }
+#pragma unroll
+  for (int q = 0; q < NE; ++q) lds[tid + q * kFftThreads] = v[q];
+  __syncthreads();
+  RadixSeq<L>::template run<INV, C, C, kFftThreads>(lds, tw);
+  for (int e = tid; e < a.Lout * C; e += kFftThreads) {
+    const int c = e % C, q = e / C;
+    const int l = q < a.out_lo ? q : q + a.out_gap;
+    base[(int64_t)l * a.I + c] = lds[l * C + c];
+  }
+}
+
+// q / d via a float reciprocal of d: (q + 1/2) / d lies at least 1/(2d)
+// away from an integer, and the two roundings move it by less than
+// (q/d + 1) 2^-23, so the truncation is exact whenever q + d < 2^22.
+__device__ __forceinline__ int qdiv(int q, float inv) { return (int)(((float)q + 0.5f) * inv); }
+
+// Compile-time forward x pass: 16 lines per workgroup (line n = (z Ny + y) P + p).
+template <int L>
+__global__ void __launch_bounds__(kFftThreads)
+k_pre_fftx_ct(PreArgs a, float inv_nx, float inv_p) {
+  constexpr int C = 16, S = 17;
+  __shared__ float2 lds[L * S];
+  __shared__ float2 tw[L];
+  const LineGeom &g = a.g;
+  const int tid = threadIdx.x;
+  const int line0 = blockIdx.x * C;
+  const int nlines = g.Nz * g.Ny * a.P;
+  const size_t nvox = (size_t)g.Nz * g.Ny * g.Nx;
+  for (int m = tid; m < L; m += kFftThreads) tw[m] = a.tw[m];
+  for (int e = tid; e < (L - g.Nx) * C; e += kFftThreads) {
+    const int c = e % C, r = e / C;
+    lds[((g.Nx - g.hx) + r) * S + c] = make_float2(0.f, 0.f);
+  }
+  for (int e = tid; e < C * g.Nx; e += kFftThreads) {
+    const int c = qdiv(e, inv_nx);
+    const int xq = e - c * g.Nx;
+    const int line = line0 + c;
+    float2 v = make_float2(0.f, 0.f);
+    if (line < nlines) {
+      const int zy = qdiv(line, inv_p);
+      const int p = line - zy * a.P;
+      const int z = zy / g.Ny, y = zy - z * g.Ny;
+      const int b = p / a.K, k = p - b * a.K;
+      const size_t vox = (size_t)zy * g.Nx + xq;
+      v = a.x[(size_t)k * nvox + vox];
+      if (a.smaps) v = cmul(a.smaps[(size_t)a.coils.idx[b] * nvox + vox], v);
+      const float sc = a.dx[xq] * a.dy[y] * a.dz[z];
+      v.x *= sc;
+      v.y *= sc;
+    }
+    lds[fine_pos(xq, g.hx, L) * S + c] = v;
+  }
+  __syncthreads();
+  RadixSeq<L>::template run<false, C, S, kFftThreads>(lds, tw);
+  for (int e = tid; e < C * L; e += kFftThreads) {
+    const int l = e % L, c = e / L;
+    const int line = line0 + c;
+    if (line >= nlines) continue;
+    const int zy = qdiv(line, inv_p);
+    const int p = line - zy * a.P;
+    const int z = zy / g.Ny, y = zy - z * g.Ny;
+    const size_t zf = fine_pos(z, g.hz, g.nfz), yf = fine_pos(y, g.hy, g.nfy);
+    a.grid[(((size_t)p * g.nfz + zf) * g.nfy + yf) * L + l] = lds[l * S + c];
+  }
+}
+
+struct CropArgs {
+  float2 *grid;     // [P][nfz][nfy][nfx]
+  int P;
+  const float2 *tw;
+  LineGeom g;
+};
+
+// Compile-time inverse x pass over the P Nz Ny image lines (line n = (p Nz
+// + z) Ny + y): the N_x image samples of each transformed line are written
+// back to the first N_x cells of the same line, in image order.
+template <int L>
+__global__ void __launch_bounds__(kFftThreads)
+k_ifftx_crop_ct(CropArgs a, float inv_nx) {
+  constexpr int C = 16, S = 17;
+  __shared__ float2 lds[L * S];
+  __shared__ float2 tw[L];
+  const LineGeom &g = a.g;
+  const int tid = threadIdx.x;
+  const int line0 = blockIdx.x * C;
+  const int nlines = a.P * g.Nz * g.Ny;
+  for (int m = tid; m < L; m += kFftThreads) tw[m] = a.tw[m];
+  auto line_base = [&](int line) -> size_t {
+    const int y = line % g.Ny, pz = line / g.Ny;
+    const int z = pz % g.Nz, p = pz / g.Nz;
+    const size_t zf = fine_pos(z, g.hz, g.nfz), yf = fine_pos(y, g.hy, g.nfy);
+    return (((size_t)p * g.nfz + zf) * g.nfy + yf) * L;
+  };
+  for (int e = tid; e < C * L; e += kFftThreads) {
+    const int l = e % L, c = e / L;
+    const int line = line0 + c;
+    lds[l * S + c] = line < nlines ? a.grid[line_base(line) + l] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  RadixSeq<L>::template run<true, C, S, kFftThreads>(lds, tw);
+  for (int e = tid; e < C * g.Nx; e += kFftThreads) {
+    const int c = qdiv(e, inv_nx);
+    const int xq = e - c * g.Nx;
+    const int line = line0 + c;
+    if (line >= nlines) continue;
+    a.grid[line_base(line) + xq] = lds[fine_pos(xq, g.hx, L) * S + c];
+  }
+}
+
+// xout[k] (+)= sum_b conj(S_b) h_{b,k} / deapodisation, h the cropped lines.
+__global__ void k_combine(PostArgs a) {
+  const LineGeom &g = a.g;
+  const size_t nvox = (size_t)g.Nz * g.Ny * g.Nx;
+  const size_t n = (size_t)a.K * nvox;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const int k = (int)(i / nvox);
+    const size_t vox = i - (size_t)k * nvox;
+    const int xq = (int)(vox % g.Nx);
+    const size_t zy = vox / g.Nx;
+    const int y = (int)(zy % g.Ny), z = (int)(zy / g.Ny);
+    const size_t zf = fine_pos(z, g.hz, g.nfz), yf = fine_pos(y, g.hy, g.nfy);
+    float2 acc = make_float2(0.f, 0.f);
+    for (int b = 0; b < a.B; ++b) {
+      const int p = b * a.K + k;
+      const float2 h = a.grid[(((size_t)p * g.nfz + zf) * g.nfy + yf) * g.nfx + xq];
+      if (a.smaps) acc = cadd(acc, cmulc(h, a.smaps[(size_t)a.coils.idx[b] * nvox + vox]));
+      else acc = cadd(acc, h);
+    }
+    const float sc = a.dx[xq] * a.dy[y] * a.dz[z];
+    acc.x *= sc;
+    acc.y *= sc;
+    if (a.accumulate) acc = cadd(acc, a.xout[i]);
+    a.xout[i] = acc;
+  }
+}
+
+bool fft_len_ct(int L) {
+  switch (L) {
+    case 64: case 128: case 192: case 256: case 320: case 384: case 448: return true;
+    default: return false;
   }
 }
 
@@ -233,7 +399,7 @@ int cols_for(int L, int cap) {
   return c;
 }
 
-size_t lds_bytes(int L, int C) { return ((size_t)L * C + L) * sizeof(float2); }
+size_t lds_bytes(int L, int S) { return ((size_t)L * S + L) * sizeof(float2); }
 
 }  // namespace
 
@@ -247,16 +413,33 @@ hipError_t launch_pre_fftx(const sdn_plan_s &p, const float2 *x, int K, const fl
   a.P = B * K;
   a.g = line_geom(p);
   const int L = a.g.nfx;
-  const int cap = kFftLdsElems / L - 1;      // columns that fit beside the twiddles
-  a.Pc = std::min(a.P, cap);
-  a.NL = std::max(1, std::min(cap / a.Pc, 16));
   a.grid = grid;
   a.dx = p.dinv[0]; a.dy = p.dinv[1]; a.dz = p.dinv[2];
   a.tw = p.tw[0];
   a.rp = p.rp[0];
-  const int nlines = a.g.Nz * a.g.Ny;
-  dim3 grd((nlines + a.NL - 1) / a.NL, (a.P + a.Pc - 1) / a.Pc);
-  hipLaunchKernelGGL(k_pre_fftx, grd, dim3(kFftThreads), lds_bytes(L, a.NL * a.Pc), st, a);
+  const int64_t nl_all = (int64_t)a.g.Nz * a.g.Ny * a.P;
+  if (fft_len_ct(L) && nl_all + a.P < (1 << 22)) {
+    const int64_t nl = nl_all;
+    const float inv_nx = 1.0f / a.g.Nx, inv_p = 1.0f / a.P;
+    dim3 grd((unsigned)((nl + 15) / 16));
+#define SDN_PRE_CT(LEN) \
+  case LEN: hipLaunchKernelGGL(k_pre_fftx_ct<LEN>, grd, dim3(kFftThreads), 0, st, a, inv_nx, inv_p); break;
+    switch (L) {
+      SDN_PRE_CT(64) SDN_PRE_CT(128) SDN_PRE_CT(192) SDN_PRE_CT(256) SDN_PRE_CT(320)
+      SDN_PRE_CT(384) SDN_PRE_CT(448)
+    }
+#undef SDN_PRE_CT
+    return hipGetLastError();
+  }
+  a.NL = std::max(1, std::min(kFftLdsElems / L - 2, 32));   // columns beside twiddles
+  a.S = a.NL | 1;
+  a.grid = grid;
+  a.dx = p.dinv[0]; a.dy = p.dinv[1]; a.dz = p.dinv[2];
+  a.tw = p.tw[0];
+  a.rp = p.rp[0];
+  const int64_t nlines = (int64_t)a.g.Nz * a.g.Ny * a.P;
+  dim3 grd((unsigned)((nlines + a.NL - 1) / a.NL));
+  hipLaunchKernelGGL(k_pre_fftx, grd, dim3(kFftThreads), lds_bytes(L, a.S), st, a);
   return hipGetLastError();
 }
 
@@ -272,10 +455,39 @@ hipError_t launch_post_ifftx(const sdn_plan_s &p, const float2 *grid, int K,
   a.P = B * K;
   a.g = line_geom(p);
   const int L = a.g.nfx;
-  const int cap = kFftLdsElems / L - 1;
+  a.xout = xout;
+  a.accumulate = accumulate;
+  a.dx = p.dinv[0]; a.dy = p.dinv[1]; a.dz = p.dinv[2];
+  a.tw = p.tw[0];
+  a.rp = p.rp[0];
+  if (fft_len_ct(L)) {
+    CropArgs c;
+    c.grid = const_cast<float2 *>(grid);
+    c.P = a.P;
+    c.tw = p.tw[0];
+    c.g = a.g;
+    const int64_t nl = (int64_t)a.P * a.g.Nz * a.g.Ny;
+    const float inv_nx = 1.0f / a.g.Nx;
+    dim3 grd((unsigned)((nl + 15) / 16));
+#define SDN_CROP_CT(LEN) \
+  case LEN: hipLaunchKernelGGL(k_ifftx_crop_ct<LEN>, grd, dim3(kFftThreads), 0, st, c, inv_nx); break;
+    switch (L) {
+      SDN_CROP_CT(64) SDN_CROP_CT(128) SDN_CROP_CT(192) SDN_CROP_CT(256) SDN_CROP_CT(320)
+      SDN_CROP_CT(384) SDN_CROP_CT(448)
+    }
+#undef SDN_CROP_CT
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t n = (size_t)K * a.g.Nz * a.g.Ny * a.g.Nx;
+    const unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 1u << 16);
+    hipLaunchKernelGGL(k_combine, dim3(blocks), dim3(256), 0, st, a);
+    return hipGetLastError();
+  }
+  const int cap = kFftLdsElems / L - 2;
   if (K > cap) return hipErrorInvalidValue;
   a.Bc = std::max(1, std::min(B, cap / K));
   a.NL = std::max(1, std::min(cap / (a.Bc * K), 16));
+  a.S = (a.NL * a.Bc * K) | 1;
   a.xout = xout;
   a.accumulate = accumulate;
   a.dx = p.dinv[0]; a.dy = p.dinv[1]; a.dz = p.dinv[2];
@@ -283,7 +495,7 @@ hipError_t launch_post_ifftx(const sdn_plan_s &p, const float2 *grid, int K,
   a.rp = p.rp[0];
   const int nlines = a.g.Nz * a.g.Ny;
   dim3 grd((nlines + a.NL - 1) / a.NL);
-  hipLaunchKernelGGL(k_post_ifftx, grd, dim3(kFftThreads), lds_bytes(L, a.NL * a.Bc * K), st, a);
+  hipLaunchKernelGGL(k_post_ifftx, grd, dim3(kFftThreads), lds_bytes(L, a.S), st, a);
   return hipGetLastError();
 }
 
@@ -295,20 +507,20 @@ hipError_t launch_fft_axis(const sdn_plan_s &p, float2 *grid, int P, int axis, b
   a.L = ax.nf;
   a.tw = p.tw[axis];
   a.rp = p.rp[axis];
-  const int64_t nfx = p.ax[0].nf, nfy = p.ax[1].nf;
-  int outer;
+  const int64_t nfx = p.ax[0].nf, nfy = p.ax[1].nf, nfz = p.ax[2].nf;
+  a.so1 = nfx * nfy * nfz;   // one channel's grid
   if (axis == 1) {
-    a.I = nfx * P;
-    a.so = (int64_t)ax.nf * a.I;
-    // only the image z planes carry data in either direction
+    // planes: only the image z planes carry data in either direction
     const Axis &az = p.ax[2];
-    outer = az.N;
+    a.I = nfx;
+    a.O2 = az.N;
+    a.so2 = nfy * nfx;
     a.o_lo = az.N - az.half;
     a.o_gap = az.nf - az.N;
   } else {
-    a.I = nfy * nfx * P;
-    a.so = 0;
-    outer = 1;
+    a.I = nfy * nfx;
+    a.O2 = 1;
+    a.so2 = 0;
     a.o_lo = 1;
     a.o_gap = 0;
   }
@@ -328,6 +540,28 @@ hipError_t launch_fft_axis(const sdn_plan_s &p, float2 *grid, int P, int axis, b
     a.Lout = ax.nf;
     a.out_lo = ax.nf;
     a.out_gap = 0;
+  }
+  const int64_t outer = (int64_t)P * a.O2;
+  if (outer > 65535) return hipErrorInvalidValue;
+  if (a.I % 16 == 0) {
+    a.C = 16;
+    dim3 grd((unsigned)(a.I / 16), (unsigned)outer);
+#define SDN_AXIS_CT(LEN)                                                                     \
+  case LEN:                                                                                  \
+    if (inverse) hipLaunchKernelGGL((k_fft_axis_ct<true, LEN>), grd, dim3(kFftThreads), 0, st, a);  \
+    else hipLaunchKernelGGL((k_fft_axis_ct<false, LEN>), grd, dim3(kFftThreads), 0, st, a);         \
+    return hipGetLastError();
+    switch (a.L) {
+      SDN_AXIS_CT(64)
+      SDN_AXIS_CT(128)
+      SDN_AXIS_CT(192)
+      SDN_AXIS_CT(256)
+      SDN_AXIS_CT(320)
+      SDN_AXIS_CT(384)
+      SDN_AXIS_CT(448)
+      default: break;
+    }
+#undef SDN_AXIS_CT
   }
   int C = cols_for(a.L, 64);
   while (C > 1 && a.I % C) C /= 2;

@@ -1,7 +1,7 @@
 // Batched mixed-radix Stockham FFT of C columns of length L held in LDS.
 //
-// Layout: element (l, c) at lds[l * C + c]; a workgroup transforms all C
-// columns together.  Each radix-R pass reads every thread's butterflies into
+// Layout: element (l, c) at lds[l * S + c] (row stride S >= C); a
+// workgroup transforms all C columns together.  Each radix-R pass reads every thread's butterflies into
 // registers, synchronises, then writes them to their self-sorting (Stockham)
 // positions, so the transform runs in place in one LDS buffer and leaves
 // the output in natural order.
@@ -118,7 +118,8 @@ __device__ __forceinline__ void dft(float2 (&v)[R]) {
 }
 
 template <int R, bool INV>
-__device__ __forceinline__ void fft_pass(float2 *lds, int L, int C, int Ns, const float2 *tw) {
+__device__ __forceinline__ void fft_pass(float2 *lds, int L, int C, int S, int Ns,
+                                         const float2 *tw) {
   constexpr int MAXB = (kFftLdsElems / R + kFftThreads - 1) / kFftThreads;
   const int nbf = L / R;
   const int total = nbf * C;
@@ -131,7 +132,7 @@ __device__ __forceinline__ void fft_pass(float2 *lds, int L, int C, int Ns, cons
     if (b < total) {
       const int c = b % C, j = b / C;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[q][r] = lds[(j + r * nbf) * C + c];
+      for (int r = 0; r < R; ++r) v[q][r] = lds[(j + r * nbf) * S + c];
     }
   }
   __syncthreads();
@@ -151,25 +152,101 @@ __device__ __forceinline__ void fft_pass(float2 *lds, int L, int C, int Ns, cons
       dft<R, INV>(v[q]);
       const int d = (j / Ns) * Ns * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) lds[(d + r * Ns) * C + c] = v[q][r];
+      for (int r = 0; r < R; ++r) lds[(d + r * Ns) * S + c] = v[q][r];
     }
   }
   __syncthreads();
 }
 
+// ------------------------------------------------------------------------
+// Compile-time variant for the common fine-grid lengths: L, C, the row
+// stride S and every pass's Ns are constants, so index arithmetic folds and
+// each thread holds exactly the butterflies it needs.
+template <int R, bool INV, int L, int C, int S, int Ns, int NT>
+__device__ __forceinline__ void fft_pass_ct(float2 *lds, const float2 *tw) {
+  constexpr int nbf = L / R;
+  constexpr int total = nbf * C;
+  constexpr int MAXB = (total + NT - 1) / NT;
+  constexpr int tstride = L / (Ns * R);
+  const int tid = threadIdx.x;
+  float2 v[MAXB][R];
+#pragma unroll
+  for (int q = 0; q < MAXB; ++q) {
+    const int b = tid + q * NT;
+    if (total % NT == 0 || b < total) {
+      const int c = b % C, j = b / C;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q][r] = lds[(j + r * nbf) * S + c];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < MAXB; ++q) {
+    const int b = tid + q * NT;
+    if (total % NT == 0 || b < total) {
+      const int c = b % C, j = b / C;
+      const int k = j % Ns;
+      if constexpr (Ns > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          const float2 w = tw[r * k * tstride];
+          v[q][r] = INV ? cmulc(v[q][r], w) : cmul(v[q][r], w);
+        }
+      }
+      dft<R, INV>(v[q]);
+      const int d = (j / Ns) * Ns * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds[(d + r * Ns) * S + c] = v[q][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <bool INV, int L, int C, int S, int NT, int Ns, int... Rs>
+struct FftPasses {
+  static __device__ __forceinline__ void run(float2 *, const float2 *) {}
+};
+template <bool INV, int L, int C, int S, int NT, int Ns, int R, int... Rs>
+struct FftPasses<INV, L, C, S, NT, Ns, R, Rs...> {
+  static __device__ __forceinline__ void run(float2 *lds, const float2 *tw) {
+    fft_pass_ct<R, INV, L, C, S, Ns, NT>(lds, tw);
+    FftPasses<INV, L, C, S, NT, Ns * R, Rs...>::run(lds, tw);
+  }
+};
+
+// Radix sequences of the specialised lengths (the host radix_plan order).
+template <int L>
+struct RadixSeq;
+#define SDN_RADIX_SEQ(LEN, ...)                                                      \
+  template <>                                                                        \
+  struct RadixSeq<LEN> {                                                             \
+    template <bool INV, int C, int S, int NT>                                        \
+    static __device__ __forceinline__ void run(float2 *lds, const float2 *tw) {      \
+      FftPasses<INV, LEN, C, S, NT, 1, __VA_ARGS__>::run(lds, tw);                   \
+    }                                                                                \
+  };
+SDN_RADIX_SEQ(64, 8, 8)
+SDN_RADIX_SEQ(128, 4, 4, 8)
+SDN_RADIX_SEQ(192, 8, 8, 3)
+SDN_RADIX_SEQ(256, 4, 8, 8)
+SDN_RADIX_SEQ(320, 8, 8, 5)
+SDN_RADIX_SEQ(384, 6, 8, 8)
+SDN_RADIX_SEQ(448, 8, 8, 7)
+#undef SDN_RADIX_SEQ
+
 // Transform all C columns; `tw` = exp(-2 pi i m / L) (inverse uses conj).
 template <bool INV>
-__device__ void fft_lds(float2 *lds, int L, int C, const RadixPlan &rp, const float2 *tw) {
+__device__ void fft_lds(float2 *lds, int L, int C, int S, const RadixPlan &rp, const float2 *tw) {
   int Ns = 1;
   for (int p = 0; p < rp.n; ++p) {
     switch (rp.r[p]) {
-      case 2: fft_pass<2, INV>(lds, L, C, Ns, tw); break;
-      case 3: fft_pass<3, INV>(lds, L, C, Ns, tw); break;
-      case 4: fft_pass<4, INV>(lds, L, C, Ns, tw); break;
-      case 5: fft_pass<5, INV>(lds, L, C, Ns, tw); break;
-      case 6: fft_pass<6, INV>(lds, L, C, Ns, tw); break;
-      case 7: fft_pass<7, INV>(lds, L, C, Ns, tw); break;
-      default: fft_pass<8, INV>(lds, L, C, Ns, tw); break;
+      case 2: fft_pass<2, INV>(lds, L, C, S, Ns, tw); break;
+      case 3: fft_pass<3, INV>(lds, L, C, S, Ns, tw); break;
+      case 4: fft_pass<4, INV>(lds, L, C, S, Ns, tw); break;
+      case 5: fft_pass<5, INV>(lds, L, C, S, Ns, tw); break;
+      case 6: fft_pass<6, INV>(lds, L, C, S, Ns, tw); break;
+      case 7: fft_pass<7, INV>(lds, L, C, S, Ns, tw); break;
+      default: fft_pass<8, INV>(lds, L, C, S, Ns, tw); break;
     }
     Ns *= rp.r[p];
   }

@@ -1,10 +1,20 @@
 // Kernel interpolation (type 2) and spreading (type 1) between the fine
 // grids and the nonuniform points, with the temporal-subspace mix fused in.
 //
-// Points are read in plan order (sorted by fine-grid tile), so neighbouring
-// threads touch neighbouring grid cells.  The fine grid is [z][y][x][p]
-// with channel p = b K + k innermost: the K channels of one coil at one
-// cell are contiguous.
+// Fine grids are channel-major, [p][z][y][x] with p = b K + k, so one
+// channel of one tile is a compact working set.  Both kernels work tile by
+// tile (tiles of bx x by x bz fine cells):
+//
+// * interpolation: a workgroup takes the points whose first node lies in
+//   one tile (a crowded tile is split into several items) and, channel by
+//   channel, stages the tile plus its W-1 halo in LDS with coalesced loads,
+//   then every lane interpolates its points from LDS and accumulates the
+//   subspace mix y_b = sum_k V[t][k] u_{b,k} in registers;
+// * spreading: a workgroup owns one output tile.  It walks the plan's list
+//   of points whose kernel support touches the tile, accumulates their
+//   contributions (with the conjugate mix) into the tile in LDS, and writes
+//   the tile once with coalesced stores - no global atomics and no separate
+//   clear of the grid, since every tile is written exactly once.
 #include <algorithm>
 
 #include "fft_lds.h"
@@ -34,28 +44,42 @@ __device__ __forceinline__ void unpack_l0(float bits, int &lx, int &ly, int &lz)
   lz = (int)((u >> 20) & 1023u);
 }
 
-struct GridGeom {
+// q = e / d via a float reciprocal of d: exact whenever e + d < 2^22 (the
+// rounding error stays below the 1/(2d) distance to the next integer);
+// used for tile-local indices only (e below 2^16).
+__device__ __forceinline__ int fdiv(int e, float inv) { return (int)(((float)e + 0.5f) * inv); }
+
+__device__ __forceinline__ int wrap(int v, int n) {
+  v = v >= n ? v - n : v;
+  return v >= n ? v - n : v;
+}
+
+struct TileGeom {
   int nfx, nfy, nfz;
-  int tbx, tby, tbz;      // tile edges
-  int ntx, nty;           // tiles along x and y
+  int bx, by, bz;
+  int ntx, nty;
+  size_t G;            // cells of one channel's grid
 };
 
-GridGeom grid_geom(const sdn_plan_s &p) {
-  GridGeom g;
+TileGeom tile_geom(const sdn_plan_s &p) {
+  TileGeom g;
   g.nfx = p.ax[0].nf; g.nfy = p.ax[1].nf; g.nfz = p.ax[2].nf;
-  g.tbx = p.ax[0].tile; g.tby = p.ax[1].tile; g.tbz = p.ax[2].tile;
+  g.bx = p.ax[0].tile; g.by = p.ax[1].tile; g.bz = p.ax[2].tile;
   g.ntx = p.ax[0].ntile; g.nty = p.ax[1].ntile;
+  g.G = (size_t)g.nfx * g.nfy * g.nfz;
   return g;
 }
 
 struct InterpDev {
   const float4 *rec;
   const int2 *pidx;
+  const int4 *work;
   int M;
-  GridGeom g;
+  TileGeom g;
+  float inv_px, inv_py;
   const float2 *grid;
-  int P, groups, K;
-  const float2 *V;
+  int K;               // channels per group
+  const float2 *V;     // [T][K] (mix mode)
   float2 *y;
   const float2 *d;
   const float *w;
@@ -63,88 +87,105 @@ struct InterpDev {
   double *loss;
 };
 
-// One thread per (point, group).  A group is the K channels of one coil
-// (mix mode: output y_b = sum_k V[t][k] u_{b,k}) or a single channel.
-template <int W, int NC, int KG, bool MIX, bool DC>
-__global__ void __launch_bounds__(256) k_interp(InterpDev a, KerCoef kc) {
-  const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = (int)(gt / a.groups);
-  const int grp = (int)(gt % a.groups);
-  double my_loss = 0.0;
-  if (j < a.M) {
-    const float4 r = a.rec[j];
-    const int2 id = a.pidx[j];
-    int lx, ly, lz;
-    unpack_l0(r.w, lx, ly, lz);
-    float wx[W], wy[W], wz[W];
-    axis_weights<W, NC>(r.x, kc, wx);
-    axis_weights<W, NC>(r.y, kc, wy);
-    axis_weights<W, NC>(r.z, kc, wz);
-    const GridGeom &g = a.g;
-    float2 acc[KG];
-#pragma unroll
-    for (int q = 0; q < KG; ++q) acc[q] = make_float2(0.f, 0.f);
-    int xs[W];
-#pragma unroll
-    for (int i = 0; i < W; ++i) {
-      const int x = lx + i;
-      xs[i] = x >= g.nfx ? x - g.nfx : x;
+constexpr int kThreads = 256;
+constexpr int kIThreads = 512;                // interpolation workgroup
+constexpr int kPPT = kItemCap / kIThreads;    // points per thread per item
+
+// grid = (items, groups).  Mix mode: a group is one coil and its K channels,
+// output y_b = sum_k V[t][k] u_k (+ DC epilogue), the running sums kept in
+// LDS behind the staged tile.  Otherwise a group is K independent channels
+// with outputs y_{gK+k} = u_k.
+template <int W, int NC, bool MIX, bool DC>
+__global__ void __launch_bounds__(kIThreads) k_interp(InterpDev a, KerCoef kc) {
+  extern __shared__ float2 tile[];
+  const TileGeom &g = a.g;
+  const int4 wi = a.work[blockIdx.x];
+  const int grp = blockIdx.y;
+  const int tid = threadIdx.x;
+  const int tz = wi.x / (g.ntx * g.nty);
+  const int rem = wi.x - tz * (g.ntx * g.nty);
+  const int ty = rem / g.ntx, tx = rem - ty * g.ntx;
+  const int ox = tx * g.bx, oy = ty * g.by, oz = tz * g.bz;
+  const int PX = g.bx + W - 1, PY = g.by + W - 1, PZ = g.bz + W - 1;
+  const int ncell = PX * PY * PZ;
+  float2 *acc = tile + ncell;   // [kItemCap] running subspace sums (mix mode)
+
+  if constexpr (MIX) {
+    for (int q = tid; q < wi.z; q += kIThreads) acc[q] = make_float2(0.f, 0.f);
+  }
+  for (int k = 0; k < a.K; ++k) {
+    const float2 *gp = a.grid + (size_t)(grp * a.K + k) * g.G;
+    for (int e = tid; e < ncell; e += kIThreads) {
+      const int row = fdiv(e, a.inv_px);
+      const int cx = e - row * PX;
+      const int cz = fdiv(row, a.inv_py);
+      const int cy = row - cz * PY;
+      const int gx = wrap(ox + cx, g.nfx), gy = wrap(oy + cy, g.nfy), gz = wrap(oz + cz, g.nfz);
+      tile[e] = gp[((size_t)gz * g.nfy + gy) * g.nfx + gx];
     }
-    const float2 *gbase = a.grid + (size_t)grp * KG;
+    __syncthreads();
+#pragma unroll 1
+    for (int q = tid; q < wi.z; q += kIThreads) {
+      const float4 rc = a.rec[wi.y + q];
+      const int2 id = a.pidx[wi.y + q];
+      int lx, ly, lz;
+      unpack_l0(rc.w, lx, ly, lz);
+      lx -= ox; ly -= oy; lz -= oz;
+      float wx[W], wy[W], wz[W];
+      axis_weights<W, NC>(rc.x, kc, wx);
+      axis_weights<W, NC>(rc.y, kc, wy);
+      axis_weights<W, NC>(rc.z, kc, wz);
+      float ur = 0.f, ui = 0.f;
 #pragma unroll
-    for (int az = 0; az < W; ++az) {
-      int zc = lz + az;
-      zc = zc >= g.nfz ? zc - g.nfz : zc;
+      for (int az = 0; az < W; ++az) {
 #pragma unroll
-      for (int ay = 0; ay < W; ++ay) {
-        int yc = ly + ay;
-        yc = yc >= g.nfy ? yc - g.nfy : yc;
-        const float wzy = wz[az] * wy[ay];
-        const float2 *row = gbase + ((size_t)zc * g.nfy + yc) * g.nfx * a.P;
+        for (int ay = 0; ay < W; ++ay) {
+          const float2 *row = tile + ((lz + az) * PY + (ly + ay)) * PX + lx;
+          float tr = 0.f, ti = 0.f;
 #pragma unroll
-        for (int i = 0; i < W; ++i) {
-          const float ww = wzy * wx[i];
-          const float2 *cell = row + (size_t)xs[i] * a.P;
-#pragma unroll
-          for (int q = 0; q < KG; ++q) {
-            const float2 v = cell[q];
-            acc[q].x = fmaf(ww, v.x, acc[q].x);
-            acc[q].y = fmaf(ww, v.y, acc[q].y);
+          for (int i = 0; i < W; ++i) {
+            const float2 v = row[i];
+            tr = fmaf(wx[i], v.x, tr);
+            ti = fmaf(wx[i], v.y, ti);
           }
+          const float wzy = wz[az] * wy[ay];
+          ur = fmaf(wzy, tr, ur);
+          ui = fmaf(wzy, ti, ui);
         }
       }
+      const float2 u = make_float2(ur, ui);
+      if constexpr (MIX) {
+        acc[q] = cadd(acc[q], cmul(a.V[(size_t)id.x * a.K + k], u));
+      } else {
+        a.y[(size_t)(grp * a.K + k) * a.M + id.y] = u;
+      }
     }
-    const int orig = id.y;
-    if constexpr (MIX) {
-      const float2 *vr = a.V + (size_t)id.x * a.K;
-      float2 yv = make_float2(0.f, 0.f);
-#pragma unroll
-      for (int q = 0; q < KG; ++q) yv = cadd(yv, cmul(vr[q], acc[q]));
+    __syncthreads();
+  }
+  if constexpr (MIX) {
+    double my_loss = 0.0;
+    for (int q = tid; q < wi.z; q += kIThreads) {
+      const int orig = a.pidx[wi.y + q].y;
       if constexpr (DC) {
         const float2 dv = a.d[(size_t)grp * a.M + orig];
-        const float2 df = csub(yv, dv);
+        const float2 df = csub(acc[q], dv);
         const float wt = a.w ? a.w[orig] : 1.f;
-        my_loss = (double)wt * ((double)df.x * df.x + (double)df.y * df.y);
-        a.r_plan[(size_t)grp * a.M + j] = make_float2(2.f * wt * df.x, 2.f * wt * df.y);
+        my_loss += (double)wt * ((double)df.x * df.x + (double)df.y * df.y);
+        a.r_plan[(size_t)grp * a.M + wi.y + q] = make_float2(2.f * wt * df.x, 2.f * wt * df.y);
       } else {
-        a.y[(size_t)grp * a.M + orig] = yv;
+        a.y[(size_t)grp * a.M + orig] = acc[q];
       }
-    } else {
-#pragma unroll
-      for (int q = 0; q < KG; ++q) a.y[(size_t)(grp * KG + q) * a.M + orig] = acc[q];
     }
-  }
-  if constexpr (DC) {
-    // block reduction of the loss, one double atomic per block
-    __shared__ double part[4];
-    for (int off = 32; off > 0; off >>= 1) my_loss += __shfl_down(my_loss, off, 64);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    if (lane == 0) part[wv] = my_loss;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double s = 0.0;
-      for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += part[i];
-      atomicAdd(a.loss, s);
+    if constexpr (DC) {
+      __shared__ double part[kIThreads / 64];
+      for (int off = 32; off > 0; off >>= 1) my_loss += __shfl_down(my_loss, off, 64);
+      if ((tid & 63) == 0) part[tid >> 6] = my_loss;
+      __syncthreads();
+      if (tid == 0) {
+        double s = 0.0;
+        for (int i = 0; i < kIThreads / 64; ++i) s += part[i];
+        atomicAdd(a.loss, s);
+      }
     }
   }
 }
@@ -152,91 +193,157 @@ __global__ void __launch_bounds__(256) k_interp(InterpDev a, KerCoef kc) {
 struct SpreadDev {
   const float4 *rec;
   const int2 *pidx;
-  const int4 *work;
+  const int4 *items;
+  const int *vlist;
   int M;
-  GridGeom g;
+  TileGeom g;
+  float inv_bx, inv_bxy;
   float2 *grid;
-  int P, K, Pc;
+  float2 *part;        // [slot][group][K][tile cells]
+  int groups;
+  int K;               // channels per group
+  int KC;              // channels per LDS pass
   const float2 *V;
-  const float2 *src;
+  const float2 *src;   // mix: [groups][M]; else [groups * K][M]
   int src_plan;
 };
 
-// One workgroup per (work item, channel chunk): the points of one tile (or
-// a slice of a crowded tile) are spread into an LDS copy of the tile plus
-// its (W-1)-cell halo, which is then added to the fine grid.  Tiles overlap
-// through their halos, so the write-back uses float atomics; cells that
-// stayed zero are skipped.
+constexpr int kMaxKC = 8;
+
+// grid = (items, groups).  An item is one tile's spreading list (or a slice
+// of a crowded tile's list) for one group's channels.  An unsplit item owns
+// its tile and writes it to the grid; a slice writes a partial tile to its
+// slot, summed by k_spread_reduce.
 template <int W, int NC, bool MIX>
-__global__ void __launch_bounds__(256) k_spread(SpreadDev a, KerCoef kc) {
-  extern __shared__ float2 tile[];
-  const GridGeom &g = a.g;
-  const int4 wi = a.work[blockIdx.x];
+__global__ void __launch_bounds__(kThreads) k_spread(SpreadDev a, KerCoef kc) {
+  extern __shared__ float acc[];   // [cell][KC] complex as float pairs
+  const TileGeom &g = a.g;
+  const int4 it = a.items[blockIdx.x];
+  const int T = it.x;
+  const int grp = blockIdx.y;
   const int tid = threadIdx.x;
-  const int tz = wi.x / (g.ntx * g.nty);
-  const int rem = wi.x % (g.ntx * g.nty);
-  const int ty = rem / g.ntx, tx = rem % g.ntx;
-  const int ox = tx * g.tbx, oy = ty * g.tby, oz = tz * g.tbz;
-  const int PX = g.tbx + W - 1, PY = g.tby + W - 1, PZ = g.tbz + W - 1;
-  const int ncell = PX * PY * PZ;
-  const int p0 = blockIdx.y * a.Pc;
-  const int pc = min(a.Pc, a.P - p0);
-  const int Pc = a.Pc;
-  for (int e = tid; e < ncell * Pc; e += 256) tile[e] = make_float2(0.f, 0.f);
-  __syncthreads();
-  const int slots = 256 / Pc;
-  const int slot = tid / Pc, pp = tid % Pc;
-  if (slot < slots && pp < pc) {
-    const int p = p0 + pp;
-    for (int q = slot; q < wi.z; q += slots) {
-      const int j = wi.y + q;
+  const int tz = T / (g.ntx * g.nty);
+  const int rem = T - tz * (g.ntx * g.nty);
+  const int ty = rem / g.ntx, tx = rem - ty * g.ntx;
+  const int ox = tx * g.bx, oy = ty * g.by, oz = tz * g.bz;
+  const int ex = min(g.bx, g.nfx - ox), ey = min(g.by, g.nfy - oy), ez = min(g.bz, g.nfz - oz);
+  const int ncell = g.bx * g.by * g.bz;
+  const int v0 = it.y, nv = it.z;
+  const int KC = a.KC;
+  for (int k0 = 0; k0 < a.K; k0 += KC) {
+    const int kcn = min(KC, a.K - k0);
+    for (int e = tid; e < ncell * KC * 2; e += kThreads) acc[e] = 0.f;
+    __syncthreads();
+    for (int e = tid; e < nv; e += kThreads) {
+      const int j = a.vlist[v0 + e];
       const float4 r = a.rec[j];
       const int2 id = a.pidx[j];
       const int col = a.src_plan ? j : id.y;
-      float2 val;
+      float2 val[kMaxKC];
       if constexpr (MIX) {
-        const int b = p / a.K, k = p % a.K;
-        val = cmulc(a.src[(size_t)b * a.M + col], a.V[(size_t)id.x * a.K + k]);
+        const float2 rv = a.src[(size_t)grp * a.M + col];
+#pragma unroll
+        for (int kk = 0; kk < kMaxKC; ++kk)
+          if (kk < kcn) val[kk] = cmulc(rv, a.V[(size_t)id.x * a.K + k0 + kk]);
       } else {
-        val = a.src[(size_t)p * a.M + col];
+#pragma unroll
+        for (int kk = 0; kk < kMaxKC; ++kk)
+          if (kk < kcn) val[kk] = a.src[(size_t)(grp * a.K + k0 + kk) * a.M + col];
       }
-      int lx, ly, lz;
-      unpack_l0(r.w, lx, ly, lz);
-      lx -= ox; ly -= oy; lz -= oz;
+      int l0x, l0y, l0z;
+      unpack_l0(r.w, l0x, l0y, l0z);
       float wx[W], wy[W], wz[W];
       axis_weights<W, NC>(r.x, kc, wx);
       axis_weights<W, NC>(r.y, kc, wy);
       axis_weights<W, NC>(r.z, kc, wz);
+      int lx[W], ly[W], lz[W];
+#pragma unroll
+      for (int i = 0; i < W; ++i) {
+        lx[i] = wrap(l0x + i, g.nfx) - ox;
+        ly[i] = wrap(l0y + i, g.nfy) - oy;
+        lz[i] = wrap(l0z + i, g.nfz) - oz;
+      }
 #pragma unroll
       for (int az = 0; az < W; ++az) {
+        if (lz[az] < 0 || lz[az] >= ez) continue;
 #pragma unroll
         for (int ay = 0; ay < W; ++ay) {
+          if (ly[ay] < 0 || ly[ay] >= ey) continue;
           const float wzy = wz[az] * wy[ay];
-          float2 *row = tile + ((size_t)((lz + az) * PY + (ly + ay)) * PX + lx) * Pc + pp;
+          const int rowc = (lz[az] * g.by + ly[ay]) * g.bx;
 #pragma unroll
           for (int i = 0; i < W; ++i) {
-            const float ww = wzy * wx[i];
-            atomicAdd(&row[i * Pc].x, ww * val.x);
-            atomicAdd(&row[i * Pc].y, ww * val.y);
+            if (lx[i] < 0 || lx[i] >= ex) continue;
+            const float w = wzy * wx[i];
+            float *cell = acc + (size_t)(rowc + lx[i]) * KC * 2;
+#pragma unroll
+            for (int kk = 0; kk < kMaxKC; ++kk) {
+              if (kk < kcn) {
+                atomicAdd(cell + 2 * kk, w * val[kk].x);
+                atomicAdd(cell + 2 * kk + 1, w * val[kk].y);
+              }
+            }
           }
         }
       }
     }
+    __syncthreads();
+    for (int kk = 0; kk < kcn; ++kk) {
+      const int ch = grp * a.K + k0 + kk;
+      if (it.w < 0) {
+        float2 *gp = a.grid + (size_t)ch * g.G;
+        for (int c = tid; c < ncell; c += kThreads) {
+          const int rowi = fdiv(c, a.inv_bx);
+          const int cx = c - rowi * g.bx;
+          const int cz = fdiv(c, a.inv_bxy);
+          const int cy = rowi - cz * g.by;
+          if (cx < ex && cy < ey && cz < ez) {
+            const float *sv = acc + (size_t)c * KC * 2 + 2 * kk;
+            gp[((size_t)(oz + cz) * g.nfy + (oy + cy)) * g.nfx + (ox + cx)] =
+                make_float2(sv[0], sv[1]);
+          }
+        }
+      } else {
+        float2 *pp = a.part + ((size_t)it.w * a.groups * a.K + ch) * ncell;
+        for (int c = tid; c < ncell; c += kThreads) {
+          const float *sv = acc + (size_t)c * KC * 2 + 2 * kk;
+          pp[c] = make_float2(sv[0], sv[1]);
+        }
+      }
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  for (int e = tid; e < ncell * pc; e += 256) {
-    const int q = e % pc, cell = e / pc;
-    const float2 v = tile[cell * Pc + q];
-    if (v.x == 0.f && v.y == 0.f) continue;
-    const int cx = cell % PX, cyz = cell / PX;
-    const int cy = cyz % PY, cz = cyz / PY;
-    int gx = ox + cx, gy = oy + cy, gz = oz + cz;
-    gx = gx >= g.nfx ? gx - g.nfx : gx;
-    gy = gy >= g.nfy ? gy - g.nfy : gy;
-    gz = gz >= g.nfz ? gz - g.nfz : gz;
-    float2 *dst = a.grid + (((size_t)gz * g.nfy + gy) * g.nfx + gx) * a.P + p0 + q;
-    unsafeAtomicAdd(&dst->x, v.x);
-    unsafeAtomicAdd(&dst->y, v.y);
+}
+
+// grid = (split tiles, groups): sum the partial tiles of a crowded tile.
+__global__ void __launch_bounds__(kThreads) k_spread_reduce(SpreadDev a, const int4 *splits) {
+  const TileGeom &g = a.g;
+  const int4 sp = splits[blockIdx.x];
+  const int T = sp.x;
+  const int grp = blockIdx.y;
+  const int tz = T / (g.ntx * g.nty);
+  const int rem = T - tz * (g.ntx * g.nty);
+  const int ty = rem / g.ntx, tx = rem - ty * g.ntx;
+  const int ox = tx * g.bx, oy = ty * g.by, oz = tz * g.bz;
+  const int ex = min(g.bx, g.nfx - ox), ey = min(g.by, g.nfy - oy), ez = min(g.bz, g.nfz - oz);
+  const int ncell = g.bx * g.by * g.bz;
+  for (int k = 0; k < a.K; ++k) {
+    const int ch = grp * a.K + k;
+    float2 *gp = a.grid + (size_t)ch * g.G;
+    for (int c = threadIdx.x; c < ncell; c += kThreads) {
+      const int rowi = fdiv(c, a.inv_bx);
+      const int cx = c - rowi * g.bx;
+      const int cz = fdiv(c, a.inv_bxy);
+      const int cy = rowi - cz * g.by;
+      if (cx >= ex || cy >= ey || cz >= ez) continue;
+      float sr = 0.f, si = 0.f;
+      for (int q = 0; q < sp.z; ++q) {
+        const float2 v = a.part[((size_t)(sp.y + q) * a.groups * a.K + ch) * ncell + c];
+        sr += v.x;
+        si += v.y;
+      }
+      gp[((size_t)(oz + cz) * g.nfy + (oy + cy)) * g.nfx + (ox + cx)] = make_float2(sr, si);
+    }
   }
 }
 
@@ -270,45 +377,46 @@ __global__ void k_mix_adj(const float2 *r, const float2 *V, const int32_t *frame
   out[j] = cmulc(r[j], V[(size_t)t * K + k]);
 }
 
+}  // namespace
+
+// LDS of an interpolation workgroup: the staged tile plus the running sums.
+size_t interp_lds_bytes(const sdn_plan_s &p) {
+  return ((size_t)(p.ax[0].tile + p.W - 1) * (p.ax[1].tile + p.W - 1) * (p.ax[2].tile + p.W - 1) +
+          kItemCap) * sizeof(float2);
+}
+
+namespace {
+
 template <int W, int NC>
-hipError_t interp_dispatch_kg(const InterpDev &d, const KerCoef &kc, int kg, bool mix, bool dc,
-                              dim3 grd, hipStream_t st) {
-#define SDN_INTERP(KGV)                                                                     \
-  case KGV:                                                                                 \
-    if (mix && dc)                                                                          \
-      hipLaunchKernelGGL((k_interp<W, NC, KGV, true, true>), grd, dim3(256), 0, st, d, kc); \
-    else if (mix)                                                                           \
-      hipLaunchKernelGGL((k_interp<W, NC, KGV, true, false>), grd, dim3(256), 0, st, d, kc);\
-    else                                                                                    \
-      hipLaunchKernelGGL((k_interp<W, NC, KGV, false, false>), grd, dim3(256), 0, st, d, kc);\
-    break;
-  switch (kg) {
-    SDN_INTERP(1)
-    SDN_INTERP(2)
-    SDN_INTERP(3)
-    SDN_INTERP(4)
-    SDN_INTERP(5)
-    SDN_INTERP(6)
-    SDN_INTERP(7)
-    SDN_INTERP(8)
-    default: return hipErrorInvalidValue;
-  }
-#undef SDN_INTERP
+hipError_t interp_launch(const InterpDev &d, const KerCoef &kc, bool mix, bool dc, dim3 grd,
+                         size_t lds, hipStream_t st) {
+  if (mix && dc)
+    hipLaunchKernelGGL((k_interp<W, NC, true, true>), grd, dim3(kIThreads), lds, st, d, kc);
+  else if (mix)
+    hipLaunchKernelGGL((k_interp<W, NC, true, false>), grd, dim3(kIThreads), lds, st, d, kc);
+  else
+    hipLaunchKernelGGL((k_interp<W, NC, false, false>), grd, dim3(kIThreads), lds, st, d, kc);
   return hipGetLastError();
 }
 
 }  // namespace
 
+size_t max_lds_bytes() { return 65536; }
+size_t spread_cell_bytes(const sdn_plan_s &p) {
+  return (size_t)p.ax[0].tile * p.ax[1].tile * p.ax[2].tile * sizeof(float2);
+}
+
 hipError_t launch_interp(const sdn_plan_s &p, const InterpArgs &a, hipStream_t st) {
-  if (p.M == 0) return hipSuccess;
+  if (p.M == 0 || p.nwork == 0) return hipSuccess;
   InterpDev d;
   d.rec = p.rec;
   d.pidx = p.pidx;
+  d.work = p.work;
   d.M = (int)p.M;
-  d.g = grid_geom(p);
+  d.g = tile_geom(p);
+  d.inv_px = 1.0f / (float)(d.g.bx + p.W - 1);
+  d.inv_py = 1.0f / (float)(d.g.by + p.W - 1);
   d.grid = a.grid;
-  d.P = a.P;
-  d.groups = a.groups;
   d.K = a.kg;
   d.V = a.V;
   d.y = a.y;
@@ -318,56 +426,71 @@ hipError_t launch_interp(const sdn_plan_s &p, const InterpArgs &a, hipStream_t s
   d.loss = a.loss;
   const bool mix = a.V != nullptr;
   const bool dc = a.d != nullptr;
-  const int64_t nthr = (int64_t)p.M * a.groups;
-  dim3 grd((unsigned)((nthr + 255) / 256));
+  const size_t lds = interp_lds_bytes(p);
+  if (lds > max_lds_bytes()) return hipErrorInvalidValue;
+  dim3 grd((unsigned)p.nwork, (unsigned)a.groups);
   switch (p.W) {
-    case 4: return interp_dispatch_kg<4, 8>(d, p.coef, a.kg, mix, dc, grd, st);
-    case 8: return interp_dispatch_kg<8, 12>(d, p.coef, a.kg, mix, dc, grd, st);
-    default: return interp_dispatch_kg<6, 10>(d, p.coef, a.kg, mix, dc, grd, st);
+    case 4: return interp_launch<4, 8>(d, p.coef, mix, dc, grd, lds, st);
+    case 8: return interp_launch<8, 12>(d, p.coef, mix, dc, grd, lds, st);
+    default: return interp_launch<6, 10>(d, p.coef, mix, dc, grd, lds, st);
   }
 }
 
+size_t spread_part_elems(const sdn_plan_s &p, int groups, int K) {
+  return (size_t)p.nslots * groups * K * p.ax[0].tile * p.ax[1].tile * p.ax[2].tile;
+}
+
 hipError_t launch_spread(const sdn_plan_s &p, const SpreadArgs &a, hipStream_t st) {
-  if (p.M == 0 || p.nwork == 0) return hipSuccess;
+  if (p.M == 0 || p.sitems == nullptr) return hipErrorInvalidValue;
+  if (p.nslots > 0 && a.part == nullptr) return hipErrorInvalidValue;
   SpreadDev d;
   d.rec = p.rec;
   d.pidx = p.pidx;
-  d.work = p.work;
+  d.items = p.sitems;
+  d.vlist = p.vlist;
   d.M = (int)p.M;
-  d.g = grid_geom(p);
+  d.g = tile_geom(p);
+  d.inv_bx = 1.0f / (float)d.g.bx;
+  d.inv_bxy = 1.0f / (float)(d.g.bx * d.g.by);
   d.grid = a.grid;
-  d.P = a.P;
+  d.part = a.part;
+  d.groups = a.groups;
   d.K = a.K;
   d.V = a.V;
   d.src = a.src;
   d.src_plan = a.src_plan_order ? 1 : 0;
-  const int ncell = (d.g.tbx + p.W - 1) * (d.g.tby + p.W - 1) * (d.g.tbz + p.W - 1);
-  const int max_pc = std::max(1, (int)(65536 / (sizeof(float2) * (size_t)ncell)));
-  d.Pc = std::min(a.P, std::min(max_pc, 256));
-  const size_t lds = (size_t)ncell * d.Pc * sizeof(float2);
-  dim3 grd((unsigned)p.nwork, (unsigned)((a.P + d.Pc - 1) / d.Pc));
+  const size_t cell_bytes = spread_cell_bytes(p);
+  int kc_max = (int)std::min<size_t>(kMaxKC, max_lds_bytes() / cell_bytes);
+  if (kc_max < 1) return hipErrorInvalidValue;
+  const int passes = (a.K + kc_max - 1) / kc_max;
+  d.KC = (a.K + passes - 1) / passes;
+  const size_t lds = (size_t)d.KC * cell_bytes;
+  dim3 grd((unsigned)p.nsitems, (unsigned)a.groups);
   const bool mix = a.V != nullptr;
   switch (p.W) {
     case 4:
-      if (mix) hipLaunchKernelGGL((k_spread<4, 8, true>), grd, dim3(256), lds, st, d, p.coef);
-      else hipLaunchKernelGGL((k_spread<4, 8, false>), grd, dim3(256), lds, st, d, p.coef);
+      if (mix) hipLaunchKernelGGL((k_spread<4, 8, true>), grd, dim3(kThreads), lds, st, d, p.coef);
+      else hipLaunchKernelGGL((k_spread<4, 8, false>), grd, dim3(kThreads), lds, st, d, p.coef);
       break;
     case 8:
-      if (mix) hipLaunchKernelGGL((k_spread<8, 12, true>), grd, dim3(256), lds, st, d, p.coef);
-      else hipLaunchKernelGGL((k_spread<8, 12, false>), grd, dim3(256), lds, st, d, p.coef);
+      if (mix) hipLaunchKernelGGL((k_spread<8, 12, true>), grd, dim3(kThreads), lds, st, d, p.coef);
+      else hipLaunchKernelGGL((k_spread<8, 12, false>), grd, dim3(kThreads), lds, st, d, p.coef);
       break;
     default:
-      if (mix) hipLaunchKernelGGL((k_spread<6, 10, true>), grd, dim3(256), lds, st, d, p.coef);
-      else hipLaunchKernelGGL((k_spread<6, 10, false>), grd, dim3(256), lds, st, d, p.coef);
+      if (mix) hipLaunchKernelGGL((k_spread<6, 10, true>), grd, dim3(kThreads), lds, st, d, p.coef);
+      else hipLaunchKernelGGL((k_spread<6, 10, false>), grd, dim3(kThreads), lds, st, d, p.coef);
       break;
   }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || p.nsplit == 0) return e;
+  hipLaunchKernelGGL(k_spread_reduce, dim3((unsigned)p.nsplit, (unsigned)a.groups), dim3(kThreads),
+                     0, st, d, (const int4 *)p.splits);
   return hipGetLastError();
 }
 
 hipError_t launch_fill_zero(float2 *a, size_t n, hipStream_t st) {
   if (n == 0) return hipSuccess;
-  // n complex = n/2 float4 (+ one float2 tail handled by rounding up the
-  // buffer: workspace buffers are allocated in whole float4s)
+  // n complex = n/2 float4; workspace buffers hold a whole number of float4s
   const size_t n4 = (n + 1) / 2;
   const unsigned blocks = (unsigned)std::min<size_t>((n4 + 255) / 256, 1u << 16);
   hipLaunchKernelGGL(k_fill_zero, dim3(blocks), dim3(256), 0, st, (float4 *)a, n4);

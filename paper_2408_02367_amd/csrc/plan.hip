@@ -87,7 +87,53 @@ __global__ void k_scatter(const int *__restrict__ key, const float4 *__restrict_
   pidx[pos] = make_int2(frame ? frame[j] : 0, j);
 }
 
+// Tiles of one axis touched by the W nodes l0 .. l0+W-1 (mod nf), in order.
+__device__ __forceinline__ int axis_tiles(int l0, int W, int nf, int b, int (&t)[8]) {
+  int n = 0, prev = -1;
+  for (int i = 0; i < W; ++i) {
+    int pos = l0 + i;
+    if (pos >= nf) pos -= nf;
+    const int tt = pos / b;
+    if (tt != prev) {
+      t[n++] = tt;
+      prev = tt;
+    }
+  }
+  if (n > 1 && t[n - 1] == t[0]) --n;
+  return n;
+}
+
+// Spreading lists: for every tile, the points whose kernel support touches
+// it (a point is listed under up to 2 tiles per axis when tiles are at
+// least W-1 cells wide).  Pass 1 counts, pass 2 scatters plan indices.
+__global__ void k_visit(const float4 *__restrict__ rec, int M, FoldGeom g,
+                        const int *__restrict__ offset, int *__restrict__ cursor,
+                        int *__restrict__ list) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= M) return;
+  const unsigned u = __float_as_uint(rec[j].w);
+  const int l0[3] = {(int)(u & 1023u), (int)((u >> 10) & 1023u), (int)((u >> 20) & 1023u)};
+  int tx[8], ty[8], tz[8];
+  const int nx = axis_tiles(l0[0], g.W, g.nf[0], g.tile[0], tx);
+  const int ny = axis_tiles(l0[1], g.W, g.nf[1], g.tile[1], ty);
+  const int nz = axis_tiles(l0[2], g.W, g.nf[2], g.tile[2], tz);
+  for (int a = 0; a < nz; ++a)
+    for (int c = 0; c < ny; ++c)
+      for (int i = 0; i < nx; ++i) {
+        const int key = (tz[a] * g.ntile[1] + ty[c]) * g.ntile[0] + tx[i];
+        const int slot = atomicAdd(&cursor[key], 1);
+        if (list) list[offset[key] + slot] = j;
+      }
+}
+
 void free_plan_memory(sdn_plan_s *p) {
+  for (auto &r : p->prof_ev) {
+    (void)hipEventDestroy(r.start);
+    (void)hipEventDestroy(r.stop);
+  }
+  p->prof_ev.clear();
+  for (auto e : p->ev_pool) (void)hipEventDestroy(e);
+  p->ev_pool.clear();
   for (int d = 0; d < 3; ++d) {
     if (p->dinv[d]) (void)hipFree(p->dinv[d]);
     if (p->tw[d]) (void)hipFree(p->tw[d]);
@@ -98,6 +144,15 @@ void free_plan_memory(sdn_plan_s *p) {
   if (p->pidx) (void)hipFree(p->pidx);
   if (p->frame_user) (void)hipFree(p->frame_user);
   if (p->work) (void)hipFree(p->work);
+  if (p->vlist) (void)hipFree(p->vlist);
+  if (p->sitems) (void)hipFree(p->sitems);
+  if (p->splits) (void)hipFree(p->splits);
+  if (p->part) (void)hipFree(p->part);
+  p->vlist = nullptr;
+  p->sitems = nullptr;
+  p->splits = nullptr;
+  p->part = nullptr;
+  p->part_cap = 0;
   if (p->grid) (void)hipFree(p->grid);
   if (p->kbuf) (void)hipFree(p->kbuf);
   p->rec = nullptr;
@@ -170,22 +225,33 @@ sdn_status sdn_plan_create(sdn_plan *out, const int64_t shape[3], const float *t
   p->ncoef = kernel_ncoef(o.W);
   kernel_coefficients(o.W, beta, p->ncoef, &p->coef);
   p->budget = o.workspace_budget;
-  p->max_points_per_item = o.max_points_per_item > 0 ? o.max_points_per_item : 1024;
+  p->max_points_per_item = o.max_points_per_item > 0 ? o.max_points_per_item : kItemCap;
+  if (p->max_points_per_item > kItemCap)
+    return delete p, fail(SDN_E_INVALID, "sdn_plan_create: max_points_per_item above 2048");
 
-  const int tile_edge = o.tile > 0 ? o.tile : 8;
+  // tiles: 16 x 16 x 8 fine cells (x, y, z), 16 x 16 x 4 for W = 8, unless
+  // the caller fixes an edge
+  const int tile_default[3] = {16, 16, o.W > 6 ? 4 : 8};
+  if (o.tile != 0 && (o.tile < 4 || o.tile > 32))
+    return delete p, fail(SDN_E_INVALID, "sdn_plan_create: tile edge must be in [4, 32]");
   // shape is (Nz, Ny, Nx); axis 0 = x
   for (int d = 0; d < 3; ++d) {
     Axis &a = p->ax[d];
     a.N = (int)shape[2 - d];
     a.nf = fine_size(a.N, o.sigma, o.W);
     a.half = a.N / 2;
-    a.tile = std::min(tile_edge, a.nf);
+    a.tile = std::min(o.tile > 0 ? o.tile : tile_default[d], a.nf);
     a.ntile = (a.nf + a.tile - 1) / a.tile;
     p->rp[d] = radix_plan(a.nf);
     if (a.nf > 1024 || p->rp[d].n <= 0) {
       delete p;
       return fail(SDN_E_UNSUPPORTED, "sdn_plan_create: fine grid above 1024 per axis");
     }
+  }
+
+  if (interp_lds_bytes(*p) > max_lds_bytes() || spread_cell_bytes(*p) > max_lds_bytes()) {
+    delete p;
+    return fail(SDN_E_INVALID, "sdn_plan_create: tile too large for workgroup memory");
   }
 
   sdn_status s = SDN_OK;
@@ -282,6 +348,63 @@ sdn_status sdn_plan_create(sdn_plan *out, const int64_t shape[3], const float *t
                          frame_of_point, m, offset, cursor, p->rec, p->pidx);
       s = hip_check(hipGetLastError(), "plan scatter kernel");
     }
+    // spreading lists over the sorted points: count, scan, scatter
+    if (s == SDN_OK) s = hip_check(hipMemsetAsync(cursor, 0, (size_t)nb * 4, st), "plan memset");
+    if (s == SDN_OK) {
+      hipLaunchKernelGGL(k_visit, dim3((m + 255) / 256), dim3(256), 0, st, p->rec, m, g,
+                         offset, cursor, (int *)nullptr);
+      s = hip_check(hipGetLastError(), "plan visit count kernel");
+    }
+    if (s == SDN_OK)
+      s = hip_check(hipMemcpyAsync(hcount.data(), cursor, (size_t)nb * 4, hipMemcpyDeviceToHost, st),
+                    "plan visit download");
+    if (s == SDN_OK) s = hip_check(hipStreamSynchronize(st), "plan sync");
+    // spreading items: one per tile (tiles without points still write their
+    // zeros); a crowded tile is split into several items whose partial
+    // tiles are summed afterwards
+    std::vector<int4> sitems, splits;
+    if (s == SDN_OK) {
+      int64_t acc = 0, slot = 0;
+      for (int b = 0; b < nb; ++b) {
+        hoff[b] = (int)acc;
+        const int c = hcount[b];
+        const int nch = std::max(1, (c + kSpreadCap - 1) / kSpreadCap);
+        if (nch == 1) {
+          sitems.push_back(make_int4(b, (int)acc, c, -1));
+        } else {
+          splits.push_back(make_int4(b, (int)slot, nch, 0));
+          for (int q = 0; q < nch; ++q)
+            sitems.push_back(make_int4(b, (int)acc + q * kSpreadCap,
+                                       std::min(kSpreadCap, c - q * kSpreadCap), (int)slot++));
+        }
+        acc += c;
+      }
+      if (acc > INT32_MAX - 1024) s = fail(SDN_E_UNSUPPORTED, "sdn_plan_create: too many points");
+      p->nvisit = acc;
+      p->nslots = slot;
+      std::stable_sort(sitems.begin(), sitems.end(),
+                       [](const int4 &a, const int4 &b) { return a.z > b.z; });
+      p->nsitems = (int64_t)sitems.size();
+      p->nsplit = (int64_t)splits.size();
+    }
+    if (s == SDN_OK) s = dalloc(&p->vlist, (size_t)p->nvisit, "plan spreading lists");
+    if (s == SDN_OK) s = dalloc(&p->sitems, sitems.size(), "plan spreading items");
+    if (s == SDN_OK) s = dalloc(&p->splits, splits.size(), "plan spreading items");
+    if (s == SDN_OK)
+      s = hip_check(hipMemcpyAsync(p->sitems, sitems.data(), sitems.size() * sizeof(int4),
+                                   hipMemcpyHostToDevice, st), "plan items upload");
+    if (s == SDN_OK && !splits.empty())
+      s = hip_check(hipMemcpyAsync(p->splits, splits.data(), splits.size() * sizeof(int4),
+                                   hipMemcpyHostToDevice, st), "plan items upload");
+    if (s == SDN_OK)
+      s = hip_check(hipMemcpyAsync(offset, hoff.data(), (size_t)nb * 4, hipMemcpyHostToDevice, st),
+                    "plan lists upload");
+    if (s == SDN_OK) s = hip_check(hipMemsetAsync(cursor, 0, (size_t)nb * 4, st), "plan memset");
+    if (s == SDN_OK && p->nvisit > 0) {
+      hipLaunchKernelGGL(k_visit, dim3((m + 255) / 256), dim3(256), 0, st, p->rec, m, g,
+                         offset, cursor, p->vlist);
+      s = hip_check(hipGetLastError(), "plan visit scatter kernel");
+    }
     if (s == SDN_OK) s = hip_check(hipStreamSynchronize(st), "plan sync");
   }
   for (void *q : {(void *)key, (void *)rec_tmp, (void *)count, (void *)cursor, (void *)offset,
@@ -323,6 +446,7 @@ sdn_status sdn_plan_get_info(sdn_plan p, sdn_plan_info *info) {
   info->nbins = p->nbins;
   info->nwork = p->nwork;
   info->max_bin = p->max_bin;
+  info->nvisit = p->nvisit;
   info->ncoef = p->ncoef;
   return SDN_OK;
 }

@@ -16,6 +16,8 @@ constexpr int kMaxCoef = 16;    // polynomial coefficients per kernel piece
 constexpr int kMaxB = 64;       // coils per minibatch
 constexpr int kMaxK = 8;        // subspace channels
 constexpr int kMaxRadices = 12; // FFT passes per axis
+constexpr int kItemCap = 2048;  // points per interpolation work item
+constexpr int kSpreadCap = 8192; // list entries per spreading work item
 
 // Piecewise-polynomial Kaiser-Bessel kernel: for a point with fractional
 // offset t in [0,1), the weight of its i-th node is
@@ -87,14 +89,32 @@ struct sdn_plan_s {
   float4 *rec = nullptr;     // (tx, ty, tz, bits of packed l0)
   int2 *pidx = nullptr;      // (frame, original index)
   int32_t *frame_user = nullptr;  // frame per point, user order
-  int4 *work = nullptr;      // (tile, start, count, 0)
-  int64_t nbins = 0, nwork = 0, max_bin = 0;
+  int4 *work = nullptr;      // interpolation items: (tile, start, count, 0)
+  int *vlist = nullptr;      // spreading lists: plan indices of the points whose support
+                             // touches a tile, grouped by tile
+  int4 *sitems = nullptr;    // spreading items: (tile, list start, count, partial slot or -1)
+  int4 *splits = nullptr;    // crowded tiles: (tile, first slot, slots, 0)
+  int64_t nbins = 0, nwork = 0, max_bin = 0, nvisit = 0;
+  int64_t nsitems = 0, nsplit = 0, nslots = 0;
 
   // workspace
   float2 *grid = nullptr;
   size_t grid_cap = 0;       // complex elements
   float2 *kbuf = nullptr;    // k-space scratch (residual / plain path)
   size_t kbuf_cap = 0;
+  float2 *part = nullptr;    // partial tiles of split spreading items
+  size_t part_cap = 0;
+
+  // per-stage event timing
+  struct StageEvents {
+    int stage;
+    hipEvent_t start, stop;
+  };
+  int prof = 0;
+  std::vector<StageEvents> prof_ev;
+  std::vector<hipEvent_t> ev_pool;
+  double prof_ms[SDN_NUM_STAGES] = {};
+  int64_t prof_n[SDN_NUM_STAGES] = {};
 };
 
 constexpr uint32_t kPlanMagic = 0x5d4e5546u;
@@ -103,17 +123,11 @@ namespace sdn {
 
 // ----------------------------------------------------------- kernel launchers
 // (defined in the .hip files; all enqueue on `st`)
-hipError_t launch_fold(const sdn_plan_s &p, const float *traj, int64_t M, int *key,
-                       float4 *rec_tmp, int *count, int *bad, hipStream_t st);
-hipError_t launch_scatter(const sdn_plan_s &p, const int *key, const float4 *rec_tmp,
-                          const int32_t *frame, int64_t M, const int *offset, int *cursor,
-                          hipStream_t st);
-
 hipError_t launch_fill_zero(float2 *a, size_t n, hipStream_t st);
 hipError_t launch_fill_zero_f64(double *a, size_t n, hipStream_t st);
 
+// Fine grids are channel-major: P = B K grids [p][nfz][nfy][nfx], p = b K + k.
 // Forward x-pass fused with coil multiply, deapodisation and zero padding.
-// Channels p = b*K + k, chunk [p0, p0 + pc) of P = B*K.
 hipError_t launch_pre_fftx(const sdn_plan_s &p, const float2 *x, int K, const float2 *smaps,
                            const CoilList &coils, int B, float2 *grid, hipStream_t st);
 // Adjoint x-pass fused with crop, deapodisation, conj coil multiply and the
@@ -142,17 +156,25 @@ struct InterpArgs {
   double *loss;
 };
 hipError_t launch_interp(const sdn_plan_s &p, const InterpArgs &a, hipStream_t st);
+size_t interp_lds_bytes(const sdn_plan_s &p);
+size_t spread_cell_bytes(const sdn_plan_s &p);
+size_t max_lds_bytes();
 
-// Spreading (type 1) of k-space values onto P fine grids (grid is added to).
+// Spreading (type 1) of k-space values onto groups * K channel-major fine
+// grids, which it overwrites completely.  Mix mode (V given): group b is a
+// coil, channel (b, k) receives conj(V[t][k]) src[b][j].  Otherwise channel
+// (g, k) receives src[g K + k][j].
 struct SpreadArgs {
   float2 *grid;
-  int P;
-  int K;              // channels per coil for the conj(V) mix (mix mode)
-  const float2 *V;    // [T][K] or null: no mix, channel p reads src row p
+  float2 *part;       // >= nslots * groups * K * tile cells complex
+  int groups;
+  int K;
+  const float2 *V;    // [T][K] or null
   const float2 *src;  // [rows][M]
   bool src_plan_order;
 };
 hipError_t launch_spread(const sdn_plan_s &p, const SpreadArgs &a, hipStream_t st);
+size_t spread_part_elems(const sdn_plan_s &p, int groups, int K);
 
 // Plain-path subspace mix kernels (user order).
 hipError_t launch_mix_fwd(const sdn_plan_s &p, const float2 *u, const float2 *V, int K, int k,

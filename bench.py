@@ -33,6 +33,8 @@ def _args():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 20,
                     help="points of the CPU oracle sample")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="also run one plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
 
 
@@ -164,15 +166,29 @@ def main():
         sdn.mrf_forward(plan, x, smaps, ci, V, out=yp, plain=True)
         sdn.mrf_adjoint(plan, d, smaps, ci, V, out=xo, plain=True)
 
-    _log(f"batched: {ms_step:.3f} ms/step; timing the plain path")
-    plain_step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(a.plain_steps):
+    plain_ms, plain_stages = None, None
+    if a.plain_steps > 0:
         _log(f"batched: {ms_step:.3f} ms/step; timing the plain path")
-    plain_step()
-    torch.cuda.synchronize()
-    plain_ms = (time.perf_counter() - t0) * 1e3 / a.plain_steps
+        plain_step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.plain_steps):
+            plain_step()
+        torch.cuda.synchronize()
+        plain_ms = (time.perf_counter() - t0) * 1e3 / a.plain_steps
+        # stage breakdown of one more plain step (not part of the timing above)
+        plan.profile(True)
+        plan.profile_read(reset=True)
+        plain_step()
+        plain_stages = {s: round(ms, 3) for s, (ms, n) in plan.profile_read(reset=True).items()}
+        plan.profile(False)
+    if a.calib_copy_mb > 0:
+        n = a.calib_copy_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     geo = dict(P=P, B=B, K=K, M=M, Nz=shape[0], Ny=shape[1], Nx=shape[2],
                nfz=info["fine"][0], nfy=info["fine"][1], nfx=info["fine"][2])
@@ -209,14 +225,15 @@ def main():
                                "(M=9.6M), KB W=6, sigma=2 (320^3 grid): batched DC gradient",
                    "shape": list(shape), "K": K, "B": B, "C": w["C"], "M": M, "T": w["T"],
                    "W": info["W"], "sigma": info["sigma"]},
-        "plain_ms_per_step": round(plain_ms, 3),
-        "speedup_vs_plain": round(plain_ms / ms_step, 3),
+        "plain_ms_per_step": round(plain_ms, 3) if plain_ms else None,
+        "speedup_vs_plain": round(plain_ms / ms_step, 3) if plain_ms else None,
+        "plain_stages_ms": plain_stages,
         "stages": per_stage,
         "roofline": roofline,
         "torch_peak_mem_GB": round(torch.cuda.max_memory_allocated() / 1e9, 2),
         "plan_workspace_GB": round(plan.workspace_size(B, K) / 1e9, 2),
     }
-    _log(f"plain: {plain_ms:.3f} ms/step")
+    _log(f"plain: {plain_ms} ms/step")
     if not a.no_cpu_baseline:
         _log("timing the CPU oracle sample")
         out["cpu_baseline"] = cpu_baseline(w, w["x"], w["smaps"], a.cpu_sample)

@@ -9,40 +9,22 @@
 //   one tile (a crowded tile is split into several items) and, channel by
 //   channel, stages the tile plus its W-1 halo in LDS with coalesced loads,
 //   then every lane interpolates its points from LDS and accumulates the
-//   subspace mix y_b = sum_k V[t][k] u_{b,k} in registers;
-// * spreading: a workgroup owns one output tile.  It walks the plan's list
-//   of points whose kernel support touches the tile, accumulates their
-//   contributions (with the conjugate mix) into the tile in LDS, and writes
-//   the tile once with coalesced stores - no global atomics and no separate
-//   clear of the grid, since every tile is written exactly once.
+//   subspace mix y_b = sum_k V[t][k] u_{b,k} (running sums behind the tile);
+// * spreading: a wave owns one 8 x 8 x 8 block and gathers the
+//   contributions of the points whose support touches it (the plan's list
+//   for the block) into registers, then writes the block once - no atomics,
+//   no separate clear of the grid (every block is written exactly once) and
+//   a fixed summation order.  Crowded blocks are split into several items
+//   whose partial blocks a small reduction sums.
 #include <algorithm>
 
 #include "fft_lds.h"
+#include "nodes.h"
 #include "sdn_internal.h"
 
 namespace sdn {
 
 namespace {
-
-// Node weights of one axis: piece i of the kernel polynomial at z = 2t - 1.
-template <int W, int NC>
-__device__ __forceinline__ void axis_weights(float t, const KerCoef &kc, float (&w)[W]) {
-  const float z = 2.f * t - 1.f;
-#pragma unroll
-  for (int i = 0; i < W; ++i) {
-    float acc = kc.c[i][NC - 1];
-#pragma unroll
-    for (int d = NC - 2; d >= 0; --d) acc = fmaf(acc, z, kc.c[i][d]);
-    w[i] = acc;
-  }
-}
-
-__device__ __forceinline__ void unpack_l0(float bits, int &lx, int &ly, int &lz) {
-  const unsigned u = __float_as_uint(bits);
-  lx = (int)(u & 1023u);
-  ly = (int)((u >> 10) & 1023u);
-  lz = (int)((u >> 20) & 1023u);
-}
 
 // q = e / d via a float reciprocal of d: exact whenever e + d < 2^22 (the
 // rounding error stays below the 1/(2d) distance to the next integer);
@@ -191,159 +173,184 @@ __global__ void __launch_bounds__(kIThreads) k_interp(InterpDev a, KerCoef kc) {
 }
 
 struct SpreadDev {
+  const int4 *items;   // (block, list start, count, partial slot or -1)
+  const int *vlist;
   const float4 *rec;
   const int2 *pidx;
-  const int4 *items;
-  const int *vlist;
+  const float *wts;    // per point: W weights for x, y, z
   int M;
-  TileGeom g;
-  float inv_bx, inv_bxy;
+  int nfx, nfy, nfz;
+  int nbx, nby;        // spreading blocks along x and y
+  size_t G;
   float2 *grid;
-  float2 *part;        // [slot][group][K][tile cells]
+  float2 *part;        // [slot][group][K][512]
   int groups;
-  int K;               // channels per group
-  int KC;              // channels per LDS pass
   const float2 *V;
   const float2 *src;   // mix: [groups][M]; else [groups * K][M]
   int src_plan;
 };
 
-constexpr int kMaxKC = 8;
+constexpr int kSB = kSpreadBlock;           // 8
+constexpr int kSBCells = kSB * kSB * kSB;   // 512
 
-// grid = (items, groups).  An item is one tile's spreading list (or a slice
-// of a crowded tile's list) for one group's channels.  An unsplit item owns
-// its tile and writes it to the grid; a slice writes a partial tile to its
-// slot, summed by k_spread_reduce.
-template <int W, int NC, bool MIX>
-__global__ void __launch_bounds__(kThreads) k_spread(SpreadDev a, KerCoef kc) {
-  extern __shared__ float acc[];   // [cell][KC] complex as float pairs
-  const TileGeom &g = a.g;
+// Spreading by gathering ("pull"), one wave per item: the wave owns an
+// 8 x 8 x 8 block, lane (y, x) holds the block's 8 z cells of all K
+// channels in registers, and the points of the block's list are walked one
+// at a time with every lane reading the same point.  A lane adds the point's
+// contribution when its (y, x) lies in the point's support; the z nodes are
+// wave-uniform, so the register index is resolved by a uniform branch.
+// Points are fetched 64 at a time, one per lane (so their memory latency
+// overlaps), into an LDS batch that the walk then reads by broadcast.  No
+// atomics anywhere; crowded blocks are split into items whose partial blocks
+// k_spread_reduce sums.
+template <int W, int K>
+struct PullRec {
+  static constexpr int n = 1 + 3 * W + 2 * K;     // l0, weights, values
+  static constexpr int stride = (n + 3) & ~3;      // whole float4s
+};
+
+template <int W, bool MIX, int K>
+__global__ void __launch_bounds__(64) k_spread(SpreadDev a) {
+  constexpr int RS = PullRec<W, K>::stride;
+  __shared__ float4 batch[64 * RS / 4];
+  float *bf = reinterpret_cast<float *>(batch);
   const int4 it = a.items[blockIdx.x];
-  const int T = it.x;
   const int grp = blockIdx.y;
-  const int tid = threadIdx.x;
-  const int tz = T / (g.ntx * g.nty);
-  const int rem = T - tz * (g.ntx * g.nty);
-  const int ty = rem / g.ntx, tx = rem - ty * g.ntx;
-  const int ox = tx * g.bx, oy = ty * g.by, oz = tz * g.bz;
-  const int ex = min(g.bx, g.nfx - ox), ey = min(g.by, g.nfy - oy), ez = min(g.bz, g.nfz - oz);
-  const int ncell = g.bx * g.by * g.bz;
-  const int v0 = it.y, nv = it.z;
-  const int KC = a.KC;
-  for (int k0 = 0; k0 < a.K; k0 += KC) {
-    const int kcn = min(KC, a.K - k0);
-    for (int e = tid; e < ncell * KC * 2; e += kThreads) acc[e] = 0.f;
-    __syncthreads();
-    for (int e = tid; e < nv; e += kThreads) {
-      const int j = a.vlist[v0 + e];
+  const int lane = threadIdx.x;
+  const int bzi = it.x / (a.nbx * a.nby);
+  const int rem = it.x - bzi * (a.nbx * a.nby);
+  const int byi = rem / a.nbx, bxi = rem - byi * a.nbx;
+  const int ox = bxi * kSB, oy = byi * kSB, oz = bzi * kSB;
+  const int cx = lane & (kSB - 1), cy = lane / kSB;
+  const int gx = ox + cx, gy = oy + cy;
+  const bool inside = gx < a.nfx && gy < a.nfy;
+
+  float ar[kSB][K], ai[kSB][K];
+#pragma unroll
+  for (int c = 0; c < kSB; ++c)
+#pragma unroll
+    for (int kk = 0; kk < K; ++kk) ar[c][kk] = ai[c][kk] = 0.f;
+
+  for (int b0 = 0; b0 < it.z; b0 += 64) {
+    const int nb = min(64, it.z - b0);
+    // fetch: lane L loads point b0 + L of the list
+    if (lane < nb) {
+      const int j = a.vlist[it.y + b0 + lane];
       const float4 r = a.rec[j];
       const int2 id = a.pidx[j];
+      const float *w = a.wts + (size_t)j * 3 * W;
+      float *o = bf + lane * RS;
+      o[0] = r.w;
+#pragma unroll
+      for (int i = 0; i < 3 * W; ++i) o[1 + i] = w[i];
       const int col = a.src_plan ? j : id.y;
-      float2 val[kMaxKC];
       if constexpr (MIX) {
         const float2 rv = a.src[(size_t)grp * a.M + col];
 #pragma unroll
-        for (int kk = 0; kk < kMaxKC; ++kk)
-          if (kk < kcn) val[kk] = cmulc(rv, a.V[(size_t)id.x * a.K + k0 + kk]);
+        for (int kk = 0; kk < K; ++kk) {
+          const float2 v = cmulc(rv, a.V[(size_t)id.x * K + kk]);
+          o[1 + 3 * W + 2 * kk] = v.x;
+          o[2 + 3 * W + 2 * kk] = v.y;
+        }
       } else {
 #pragma unroll
-        for (int kk = 0; kk < kMaxKC; ++kk)
-          if (kk < kcn) val[kk] = a.src[(size_t)(grp * a.K + k0 + kk) * a.M + col];
-      }
-      int l0x, l0y, l0z;
-      unpack_l0(r.w, l0x, l0y, l0z);
-      float wx[W], wy[W], wz[W];
-      axis_weights<W, NC>(r.x, kc, wx);
-      axis_weights<W, NC>(r.y, kc, wy);
-      axis_weights<W, NC>(r.z, kc, wz);
-      int lx[W], ly[W], lz[W];
-#pragma unroll
-      for (int i = 0; i < W; ++i) {
-        lx[i] = wrap(l0x + i, g.nfx) - ox;
-        ly[i] = wrap(l0y + i, g.nfy) - oy;
-        lz[i] = wrap(l0z + i, g.nfz) - oz;
-      }
-#pragma unroll
-      for (int az = 0; az < W; ++az) {
-        if (lz[az] < 0 || lz[az] >= ez) continue;
-#pragma unroll
-        for (int ay = 0; ay < W; ++ay) {
-          if (ly[ay] < 0 || ly[ay] >= ey) continue;
-          const float wzy = wz[az] * wy[ay];
-          const int rowc = (lz[az] * g.by + ly[ay]) * g.bx;
-#pragma unroll
-          for (int i = 0; i < W; ++i) {
-            if (lx[i] < 0 || lx[i] >= ex) continue;
-            const float w = wzy * wx[i];
-            float *cell = acc + (size_t)(rowc + lx[i]) * KC * 2;
-#pragma unroll
-            for (int kk = 0; kk < kMaxKC; ++kk) {
-              if (kk < kcn) {
-                atomicAdd(cell + 2 * kk, w * val[kk].x);
-                atomicAdd(cell + 2 * kk + 1, w * val[kk].y);
-              }
-            }
-          }
+        for (int kk = 0; kk < K; ++kk) {
+          const float2 v = a.src[(size_t)(grp * K + kk) * a.M + col];
+          o[1 + 3 * W + 2 * kk] = v.x;
+          o[2 + 3 * W + 2 * kk] = v.y;
         }
       }
     }
     __syncthreads();
-    for (int kk = 0; kk < kcn; ++kk) {
-      const int ch = grp * a.K + k0 + kk;
-      if (it.w < 0) {
-        float2 *gp = a.grid + (size_t)ch * g.G;
-        for (int c = tid; c < ncell; c += kThreads) {
-          const int rowi = fdiv(c, a.inv_bx);
-          const int cx = c - rowi * g.bx;
-          const int cz = fdiv(c, a.inv_bxy);
-          const int cy = rowi - cz * g.by;
-          if (cx < ex && cy < ey && cz < ez) {
-            const float *sv = acc + (size_t)c * KC * 2 + 2 * kk;
-            gp[((size_t)(oz + cz) * g.nfy + (oy + cy)) * g.nfx + (ox + cx)] =
-                make_float2(sv[0], sv[1]);
-          }
-        }
-      } else {
-        float2 *pp = a.part + ((size_t)it.w * a.groups * a.K + ch) * ncell;
-        for (int c = tid; c < ncell; c += kThreads) {
-          const float *sv = acc + (size_t)c * KC * 2 + 2 * kk;
-          pp[c] = make_float2(sv[0], sv[1]);
+    // walk: every lane reads point v of the batch
+    for (int v = 0; v < nb; ++v) {
+      float rr[RS];
+#pragma unroll
+      for (int q = 0; q < RS / 4; ++q) {
+        const float4 t = batch[v * (RS / 4) + q];
+        rr[4 * q] = t.x;
+        rr[4 * q + 1] = t.y;
+        rr[4 * q + 2] = t.z;
+        rr[4 * q + 3] = t.w;
+      }
+      // the point is the same for every lane: keep its nodes in scalar
+      // registers so that the z branch below is a scalar branch
+      int l0x, l0y, l0z;
+      unpack_l0(__int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(rr[0]))), l0x, l0y, l0z);
+      int dx = gx - l0x, dy = gy - l0y;
+      dx += dx < 0 ? a.nfx : 0;
+      dy += dy < 0 ? a.nfy : 0;
+      float wxl = 0.f, wyl = 0.f;
+#pragma unroll
+      for (int i = 0; i < W; ++i) {
+        wxl = dx == i ? rr[1 + i] : wxl;
+        wyl = dy == i ? rr[1 + W + i] : wyl;
+      }
+      const float wxy = inside ? wxl * wyl : 0.f;
+#pragma unroll
+      for (int az = 0; az < W; ++az) {
+        int zz = l0z + az;
+        zz -= zz >= a.nfz ? a.nfz : 0;
+        zz -= oz;
+        const float wz = wxy * rr[1 + 2 * W + az];
+        switch (zz) {
+#define SDN_ZCASE(C)                                                          \
+  case C:                                                                     \
+    _Pragma("unroll") for (int kk = 0; kk < K; ++kk) {                        \
+      ar[C][kk] = fmaf(wz, rr[1 + 3 * W + 2 * kk], ar[C][kk]);                \
+      ai[C][kk] = fmaf(wz, rr[2 + 3 * W + 2 * kk], ai[C][kk]);                \
+    }                                                                         \
+    break;
+          SDN_ZCASE(0) SDN_ZCASE(1) SDN_ZCASE(2) SDN_ZCASE(3)
+          SDN_ZCASE(4) SDN_ZCASE(5) SDN_ZCASE(6) SDN_ZCASE(7)
+#undef SDN_ZCASE
+          default: break;
         }
       }
     }
     __syncthreads();
   }
+  if (it.w >= 0) {
+    float2 *pp = a.part + ((size_t)it.w * a.groups + grp) * K * kSBCells;
+#pragma unroll
+    for (int kk = 0; kk < K; ++kk)
+#pragma unroll
+      for (int c = 0; c < kSB; ++c)
+        pp[(size_t)kk * kSBCells + c * 64 + lane] = make_float2(ar[c][kk], ai[c][kk]);
+    return;
+  }
+  if (!inside) return;
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) {
+    float2 *gp = a.grid + (size_t)(grp * K + kk) * a.G;
+#pragma unroll
+    for (int c = 0; c < kSB; ++c)
+      if (oz + c < a.nfz)
+        gp[((size_t)(oz + c) * a.nfy + gy) * a.nfx + gx] = make_float2(ar[c][kk], ai[c][kk]);
+  }
 }
 
-// grid = (split tiles, groups): sum the partial tiles of a crowded tile.
-__global__ void __launch_bounds__(kThreads) k_spread_reduce(SpreadDev a, const int4 *splits) {
-  const TileGeom &g = a.g;
+// grid = (split blocks, groups): sum the partial blocks of a crowded block.
+__global__ void __launch_bounds__(kThreads) k_spread_reduce(SpreadDev a, const int4 *splits, int K) {
   const int4 sp = splits[blockIdx.x];
-  const int T = sp.x;
   const int grp = blockIdx.y;
-  const int tz = T / (g.ntx * g.nty);
-  const int rem = T - tz * (g.ntx * g.nty);
-  const int ty = rem / g.ntx, tx = rem - ty * g.ntx;
-  const int ox = tx * g.bx, oy = ty * g.by, oz = tz * g.bz;
-  const int ex = min(g.bx, g.nfx - ox), ey = min(g.by, g.nfy - oy), ez = min(g.bz, g.nfz - oz);
-  const int ncell = g.bx * g.by * g.bz;
-  for (int k = 0; k < a.K; ++k) {
-    const int ch = grp * a.K + k;
-    float2 *gp = a.grid + (size_t)ch * g.G;
-    for (int c = threadIdx.x; c < ncell; c += kThreads) {
-      const int rowi = fdiv(c, a.inv_bx);
-      const int cx = c - rowi * g.bx;
-      const int cz = fdiv(c, a.inv_bxy);
-      const int cy = rowi - cz * g.by;
-      if (cx >= ex || cy >= ey || cz >= ez) continue;
-      float sr = 0.f, si = 0.f;
-      for (int q = 0; q < sp.z; ++q) {
-        const float2 v = a.part[((size_t)(sp.y + q) * a.groups * a.K + ch) * ncell + c];
-        sr += v.x;
-        si += v.y;
-      }
-      gp[((size_t)(oz + cz) * g.nfy + (oy + cy)) * g.nfx + (ox + cx)] = make_float2(sr, si);
+  const int bzi = sp.x / (a.nbx * a.nby);
+  const int rem = sp.x - bzi * (a.nbx * a.nby);
+  const int byi = rem / a.nbx, bxi = rem - byi * a.nbx;
+  const int ox = bxi * kSB, oy = byi * kSB, oz = bzi * kSB;
+  for (int e = threadIdx.x; e < K * kSBCells; e += kThreads) {
+    const int kk = e / kSBCells, cell = e - kk * kSBCells;
+    const int c = cell / 64, lane = cell - c * 64;
+    const int gx = ox + (lane & (kSB - 1)), gy = oy + lane / kSB, gz = oz + c;
+    if (gx >= a.nfx || gy >= a.nfy || gz >= a.nfz) continue;
+    float sr = 0.f, si = 0.f;
+    for (int q = 0; q < sp.z; ++q) {
+      const float2 v = a.part[(((size_t)(sp.y + q) * a.groups + grp) * K + kk) * kSBCells + cell];
+      sr += v.x;
+      si += v.y;
     }
+    a.grid[(size_t)(grp * K + kk) * a.G + ((size_t)gz * a.nfy + gy) * a.nfx + gx] =
+        make_float2(sr, si);
   }
 }
 
@@ -387,24 +394,55 @@ size_t interp_lds_bytes(const sdn_plan_s &p) {
 
 namespace {
 
+template <typename F>
+hipError_t allow_lds_fwd(F *kernel, size_t bytes);
+
+template <int W, int NC, bool MIX, bool DC>
+hipError_t interp_one(const InterpDev &d, const KerCoef &kc, dim3 grd, size_t lds, hipStream_t st) {
+  hipError_t e = allow_lds_fwd(k_interp<W, NC, MIX, DC>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_interp<W, NC, MIX, DC>), grd, dim3(kIThreads), lds, st, d, kc);
+  return hipGetLastError();
+}
+
 template <int W, int NC>
 hipError_t interp_launch(const InterpDev &d, const KerCoef &kc, bool mix, bool dc, dim3 grd,
                          size_t lds, hipStream_t st) {
-  if (mix && dc)
-    hipLaunchKernelGGL((k_interp<W, NC, true, true>), grd, dim3(kIThreads), lds, st, d, kc);
-  else if (mix)
-    hipLaunchKernelGGL((k_interp<W, NC, true, false>), grd, dim3(kIThreads), lds, st, d, kc);
-  else
-    hipLaunchKernelGGL((k_interp<W, NC, false, false>), grd, dim3(kIThreads), lds, st, d, kc);
-  return hipGetLastError();
+  if (mix && dc) return interp_one<W, NC, true, true>(d, kc, grd, lds, st);
+  if (mix) return interp_one<W, NC, true, false>(d, kc, grd, lds, st);
+  return interp_one<W, NC, false, false>(d, kc, grd, lds, st);
 }
 
 }  // namespace
 
-size_t max_lds_bytes() { return 65536; }
-size_t spread_cell_bytes(const sdn_plan_s &p) {
-  return (size_t)p.ax[0].tile * p.ax[1].tile * p.ax[2].tile * sizeof(float2);
+// Workgroup LDS limit of the current device (gfx950: 160 KB), queried once.
+size_t max_lds_bytes() {
+  static size_t cached = 0;
+  if (cached == 0) {
+    int dev = 0, v = 0;
+    size_t lim = 65536;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+        v > 0)
+      lim = (size_t)v;
+    cached = std::min<size_t>(lim, 160 * 1024);
+  }
+  return cached;
 }
+
+namespace {
+// Raise a kernel's dynamic-LDS cap when a launch needs more than 64 KB.
+template <typename F>
+hipError_t allow_lds(F *kernel, size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+template <typename F>
+hipError_t allow_lds_fwd(F *kernel, size_t bytes) {
+  return allow_lds(kernel, bytes);
+}
+}  // namespace
 
 hipError_t launch_interp(const sdn_plan_s &p, const InterpArgs &a, hipStream_t st) {
   if (p.M == 0 || p.nwork == 0) return hipSuccess;
@@ -437,54 +475,54 @@ hipError_t launch_interp(const sdn_plan_s &p, const InterpArgs &a, hipStream_t s
 }
 
 size_t spread_part_elems(const sdn_plan_s &p, int groups, int K) {
-  return (size_t)p.nslots * groups * K * p.ax[0].tile * p.ax[1].tile * p.ax[2].tile;
+  return (size_t)p.nslots * groups * K * kSBCells;
 }
+
+namespace {
+template <int W, bool MIX>
+hipError_t spread_k(const SpreadDev &d, int K, dim3 grd, hipStream_t st) {
+  switch (K) {
+#define SDN_SPK(KV) \
+  case KV: hipLaunchKernelGGL((k_spread<W, MIX, KV>), grd, dim3(64), 0, st, d); break;
+    SDN_SPK(1) SDN_SPK(2) SDN_SPK(3) SDN_SPK(4) SDN_SPK(5) SDN_SPK(6) SDN_SPK(7) SDN_SPK(8)
+#undef SDN_SPK
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+}  // namespace
 
 hipError_t launch_spread(const sdn_plan_s &p, const SpreadArgs &a, hipStream_t st) {
   if (p.M == 0 || p.sitems == nullptr) return hipErrorInvalidValue;
   if (p.nslots > 0 && a.part == nullptr) return hipErrorInvalidValue;
+  if (a.K < 1 || a.K > kMaxK) return hipErrorInvalidValue;
   SpreadDev d;
-  d.rec = p.rec;
-  d.pidx = p.pidx;
   d.items = p.sitems;
   d.vlist = p.vlist;
+  d.rec = p.rec;
+  d.pidx = p.pidx;
+  d.wts = p.wts;
   d.M = (int)p.M;
-  d.g = tile_geom(p);
-  d.inv_bx = 1.0f / (float)d.g.bx;
-  d.inv_bxy = 1.0f / (float)(d.g.bx * d.g.by);
+  d.nfx = p.ax[0].nf; d.nfy = p.ax[1].nf; d.nfz = p.ax[2].nf;
+  d.nbx = p.ax[0].nsblk; d.nby = p.ax[1].nsblk;
+  d.G = (size_t)d.nfx * d.nfy * d.nfz;
   d.grid = a.grid;
   d.part = a.part;
   d.groups = a.groups;
-  d.K = a.K;
   d.V = a.V;
   d.src = a.src;
   d.src_plan = a.src_plan_order ? 1 : 0;
-  const size_t cell_bytes = spread_cell_bytes(p);
-  int kc_max = (int)std::min<size_t>(kMaxKC, max_lds_bytes() / cell_bytes);
-  if (kc_max < 1) return hipErrorInvalidValue;
-  const int passes = (a.K + kc_max - 1) / kc_max;
-  d.KC = (a.K + passes - 1) / passes;
-  const size_t lds = (size_t)d.KC * cell_bytes;
-  dim3 grd((unsigned)p.nsitems, (unsigned)a.groups);
   const bool mix = a.V != nullptr;
+  dim3 grd((unsigned)p.nsitems, (unsigned)a.groups);
+  hipError_t e;
   switch (p.W) {
-    case 4:
-      if (mix) hipLaunchKernelGGL((k_spread<4, 8, true>), grd, dim3(kThreads), lds, st, d, p.coef);
-      else hipLaunchKernelGGL((k_spread<4, 8, false>), grd, dim3(kThreads), lds, st, d, p.coef);
-      break;
-    case 8:
-      if (mix) hipLaunchKernelGGL((k_spread<8, 12, true>), grd, dim3(kThreads), lds, st, d, p.coef);
-      else hipLaunchKernelGGL((k_spread<8, 12, false>), grd, dim3(kThreads), lds, st, d, p.coef);
-      break;
-    default:
-      if (mix) hipLaunchKernelGGL((k_spread<6, 10, true>), grd, dim3(kThreads), lds, st, d, p.coef);
-      else hipLaunchKernelGGL((k_spread<6, 10, false>), grd, dim3(kThreads), lds, st, d, p.coef);
-      break;
+    case 4: e = mix ? spread_k<4, true>(d, a.K, grd, st) : spread_k<4, false>(d, a.K, grd, st); break;
+    case 8: e = mix ? spread_k<8, true>(d, a.K, grd, st) : spread_k<8, false>(d, a.K, grd, st); break;
+    default: e = mix ? spread_k<6, true>(d, a.K, grd, st) : spread_k<6, false>(d, a.K, grd, st); break;
   }
-  hipError_t e = hipGetLastError();
   if (e != hipSuccess || p.nsplit == 0) return e;
   hipLaunchKernelGGL(k_spread_reduce, dim3((unsigned)p.nsplit, (unsigned)a.groups), dim3(kThreads),
-                     0, st, d, (const int4 *)p.splits);
+                     0, st, d, (const int4 *)p.splits, a.K);
   return hipGetLastError();
 }
 

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstring>
 
+#include "nodes.h"
 #include "sdn_internal.h"
 
 namespace sdn {
@@ -126,6 +127,27 @@ __global__ void k_visit(const float4 *__restrict__ rec, int M, FoldGeom g,
       }
 }
 
+// Kernel weights of every point (plan order), evaluated once per plan with
+// the same polynomial the grid kernels use.
+template <int W, int NC>
+__global__ void k_weights(const float4 *__restrict__ rec, int M, KerCoef kc,
+                          float *__restrict__ wts) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= M) return;
+  const float4 r = rec[j];
+  float w[W];
+  float *o = wts + (size_t)j * 3 * W;
+  axis_weights<W, NC>(r.x, kc, w);
+#pragma unroll
+  for (int i = 0; i < W; ++i) o[i] = w[i];
+  axis_weights<W, NC>(r.y, kc, w);
+#pragma unroll
+  for (int i = 0; i < W; ++i) o[W + i] = w[i];
+  axis_weights<W, NC>(r.z, kc, w);
+#pragma unroll
+  for (int i = 0; i < W; ++i) o[2 * W + i] = w[i];
+}
+
 void free_plan_memory(sdn_plan_s *p) {
   for (auto &r : p->prof_ev) {
     (void)hipEventDestroy(r.start);
@@ -145,6 +167,8 @@ void free_plan_memory(sdn_plan_s *p) {
   if (p->frame_user) (void)hipFree(p->frame_user);
   if (p->work) (void)hipFree(p->work);
   if (p->vlist) (void)hipFree(p->vlist);
+  if (p->wts) (void)hipFree(p->wts);
+  p->wts = nullptr;
   if (p->sitems) (void)hipFree(p->sitems);
   if (p->splits) (void)hipFree(p->splits);
   if (p->part) (void)hipFree(p->part);
@@ -242,6 +266,8 @@ sdn_status sdn_plan_create(sdn_plan *out, const int64_t shape[3], const float *t
     a.half = a.N / 2;
     a.tile = std::min(o.tile > 0 ? o.tile : tile_default[d], a.nf);
     a.ntile = (a.nf + a.tile - 1) / a.tile;
+    a.sblk = std::min(kSpreadBlock, a.nf);
+    a.nsblk = (a.nf + a.sblk - 1) / a.sblk;
     p->rp[d] = radix_plan(a.nf);
     if (a.nf > 1024 || p->rp[d].n <= 0) {
       delete p;
@@ -249,7 +275,7 @@ sdn_status sdn_plan_create(sdn_plan *out, const int64_t shape[3], const float *t
     }
   }
 
-  if (interp_lds_bytes(*p) > max_lds_bytes() || spread_cell_bytes(*p) > max_lds_bytes()) {
+  if (interp_lds_bytes(*p) > max_lds_bytes()) {
     delete p;
     return fail(SDN_E_INVALID, "sdn_plan_create: tile too large for workgroup memory");
   }
@@ -268,17 +294,20 @@ sdn_status sdn_plan_create(sdn_plan *out, const int64_t shape[3], const float *t
                     "plan tables upload");
   }
   p->nbins = (int64_t)p->ax[0].ntile * p->ax[1].ntile * p->ax[2].ntile;
+  p->nsbins = (int64_t)p->ax[0].nsblk * p->ax[1].nsblk * p->ax[2].nsblk;
 
   int *key = nullptr, *count = nullptr, *cursor = nullptr, *offset = nullptr, *bad = nullptr;
   float4 *rec_tmp = nullptr;
   if (s == SDN_OK && M > 0) {
     const int m = (int)M;
     const int nb = (int)p->nbins;
+    const int nsb = (int)p->nsbins;
+    const int nbmax = std::max(nb, nsb);
     s = dalloc(&key, m, "plan sort");
     if (s == SDN_OK) s = dalloc(&rec_tmp, m, "plan sort");
     if (s == SDN_OK) s = dalloc(&count, nb, "plan sort");
-    if (s == SDN_OK) s = dalloc(&cursor, nb, "plan sort");
-    if (s == SDN_OK) s = dalloc(&offset, nb, "plan sort");
+    if (s == SDN_OK) s = dalloc(&cursor, nbmax, "plan sort");
+    if (s == SDN_OK) s = dalloc(&offset, nbmax, "plan sort");
     if (s == SDN_OK) s = dalloc(&bad, 1, "plan sort");
     if (s == SDN_OK) s = dalloc(&p->rec, m, "plan points");
     if (s == SDN_OK) s = dalloc(&p->pidx, m, "plan points");
@@ -348,26 +377,45 @@ sdn_status sdn_plan_create(sdn_plan *out, const int64_t shape[3], const float *t
                          frame_of_point, m, offset, cursor, p->rec, p->pidx);
       s = hip_check(hipGetLastError(), "plan scatter kernel");
     }
-    // spreading lists over the sorted points: count, scan, scatter
-    if (s == SDN_OK) s = hip_check(hipMemsetAsync(cursor, 0, (size_t)nb * 4, st), "plan memset");
+    // per-point kernel weights
+    if (s == SDN_OK) s = dalloc(&p->wts, (size_t)m * 3 * p->W, "plan weights");
     if (s == SDN_OK) {
-      hipLaunchKernelGGL(k_visit, dim3((m + 255) / 256), dim3(256), 0, st, p->rec, m, g,
+      const dim3 grd((m + 255) / 256);
+      if (p->W == 4)
+        hipLaunchKernelGGL((k_weights<4, 8>), grd, dim3(256), 0, st, p->rec, m, p->coef, p->wts);
+      else if (p->W == 8)
+        hipLaunchKernelGGL((k_weights<8, 12>), grd, dim3(256), 0, st, p->rec, m, p->coef, p->wts);
+      else
+        hipLaunchKernelGGL((k_weights<6, 10>), grd, dim3(256), 0, st, p->rec, m, p->coef, p->wts);
+      s = hip_check(hipGetLastError(), "plan weights kernel");
+    }
+    // spreading lists over the sorted points and the spreading blocks:
+    // count, scan, scatter
+    FoldGeom gs = g;
+    for (int d = 0; d < 3; ++d) {
+      gs.tile[d] = p->ax[d].sblk;
+      gs.ntile[d] = p->ax[d].nsblk;
+    }
+    std::vector<int> scount(nsb), soff(nsb);
+    if (s == SDN_OK) s = hip_check(hipMemsetAsync(cursor, 0, (size_t)nsb * 4, st), "plan memset");
+    if (s == SDN_OK) {
+      hipLaunchKernelGGL(k_visit, dim3((m + 255) / 256), dim3(256), 0, st, p->rec, m, gs,
                          offset, cursor, (int *)nullptr);
       s = hip_check(hipGetLastError(), "plan visit count kernel");
     }
     if (s == SDN_OK)
-      s = hip_check(hipMemcpyAsync(hcount.data(), cursor, (size_t)nb * 4, hipMemcpyDeviceToHost, st),
+      s = hip_check(hipMemcpyAsync(scount.data(), cursor, (size_t)nsb * 4, hipMemcpyDeviceToHost, st),
                     "plan visit download");
     if (s == SDN_OK) s = hip_check(hipStreamSynchronize(st), "plan sync");
-    // spreading items: one per tile (tiles without points still write their
-    // zeros); a crowded tile is split into several items whose partial
-    // tiles are summed afterwards
+    // spreading items: one per block (blocks without points still write
+    // their zeros); a crowded block is split into several items whose
+    // partial blocks are summed afterwards
     std::vector<int4> sitems, splits;
     if (s == SDN_OK) {
       int64_t acc = 0, slot = 0;
-      for (int b = 0; b < nb; ++b) {
-        hoff[b] = (int)acc;
-        const int c = hcount[b];
+      for (int b = 0; b < nsb; ++b) {
+        soff[b] = (int)acc;
+        const int c = scount[b];
         const int nch = std::max(1, (c + kSpreadCap - 1) / kSpreadCap);
         if (nch == 1) {
           sitems.push_back(make_int4(b, (int)acc, c, -1));
@@ -397,11 +445,11 @@ sdn_status sdn_plan_create(sdn_plan *out, const int64_t shape[3], const float *t
       s = hip_check(hipMemcpyAsync(p->splits, splits.data(), splits.size() * sizeof(int4),
                                    hipMemcpyHostToDevice, st), "plan items upload");
     if (s == SDN_OK)
-      s = hip_check(hipMemcpyAsync(offset, hoff.data(), (size_t)nb * 4, hipMemcpyHostToDevice, st),
+      s = hip_check(hipMemcpyAsync(offset, soff.data(), (size_t)nsb * 4, hipMemcpyHostToDevice, st),
                     "plan lists upload");
-    if (s == SDN_OK) s = hip_check(hipMemsetAsync(cursor, 0, (size_t)nb * 4, st), "plan memset");
+    if (s == SDN_OK) s = hip_check(hipMemsetAsync(cursor, 0, (size_t)nsb * 4, st), "plan memset");
     if (s == SDN_OK && p->nvisit > 0) {
-      hipLaunchKernelGGL(k_visit, dim3((m + 255) / 256), dim3(256), 0, st, p->rec, m, g,
+      hipLaunchKernelGGL(k_visit, dim3((m + 255) / 256), dim3(256), 0, st, p->rec, m, gs,
                          offset, cursor, p->vlist);
       s = hip_check(hipGetLastError(), "plan visit scatter kernel");
     }

@@ -43,9 +43,13 @@ struct Axis {
   int N;      // image length
   int nf;     // fine length
   int half;   // floor(N / 2)
-  int tile;   // tile edge
-  int ntile;  // tiles along the axis
+  int tile;   // interpolation tile edge
+  int ntile;  // interpolation tiles along the axis
+  int sblk;   // spreading block edge
+  int nsblk;  // spreading blocks along the axis
 };
+
+constexpr int kSpreadBlock = 8;   // spreading blocks are 8 x 8 x 8 fine cells
 
 // Every status-returning path records a message through this.
 sdn_status fail(sdn_status s, const std::string &msg);
@@ -90,10 +94,12 @@ struct sdn_plan_s {
   int2 *pidx = nullptr;      // (frame, original index)
   int32_t *frame_user = nullptr;  // frame per point, user order
   int4 *work = nullptr;      // interpolation items: (tile, start, count, 0)
+  float *wts = nullptr;      // per point (plan order): W weights per axis, x then y then z
   int *vlist = nullptr;      // spreading lists: plan indices of the points whose support
-                             // touches a tile, grouped by tile
-  int4 *sitems = nullptr;    // spreading items: (tile, list start, count, partial slot or -1)
-  int4 *splits = nullptr;    // crowded tiles: (tile, first slot, slots, 0)
+                             // touches a spreading block, grouped by block
+  int4 *sitems = nullptr;    // spreading items: (block, list start, count, partial slot or -1)
+  int4 *splits = nullptr;    // crowded blocks: (block, first slot, slots, 0)
+  int64_t nsbins = 0;        // spreading blocks
   int64_t nbins = 0, nwork = 0, max_bin = 0, nvisit = 0;
   int64_t nsitems = 0, nsplit = 0, nslots = 0;
 
@@ -157,7 +163,6 @@ struct InterpArgs {
 };
 hipError_t launch_interp(const sdn_plan_s &p, const InterpArgs &a, hipStream_t st);
 size_t interp_lds_bytes(const sdn_plan_s &p);
-size_t spread_cell_bytes(const sdn_plan_s &p);
 size_t max_lds_bytes();
 
 // Spreading (type 1) of k-space values onto groups * K channel-major fine

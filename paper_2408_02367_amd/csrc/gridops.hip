@@ -195,23 +195,73 @@ constexpr int kSBCells = kSB * kSB * kSB;   // 512
 
 // Spreading by gathering ("pull"), one wave per item: the wave owns an
 // 8 x 8 x 8 block, lane (y, x) holds the block's 8 z cells of all K
-// channels in registers, and the points of the block's list are walked one
+// channels in registers, and the entries of the block's list are walked one
 // at a time with every lane reading the same point.  A lane adds the point's
-// contribution when its (y, x) lies in the point's support; the z nodes are
-// wave-uniform, so the register index is resolved by a uniform branch.
-// Points are fetched 64 at a time, one per lane (so their memory latency
-// overlaps), into an LDS batch that the walk then reads by broadcast.  No
-// atomics anywhere; crowded blocks are split into items whose partial blocks
+// contribution when its (y, x) lies in the point's support.  The plan sorts
+// a block's list by the z offset d of the point against the block, so the
+// walk meets runs of equal d in a fixed order: each run has its own loop,
+// in which every register index is a compile-time constant.  Entries are
+// fetched 64 at a time, one per lane (so their memory latency overlaps),
+// into an LDS batch that the walk then reads by broadcast.  No atomics
+// anywhere; crowded blocks are split into items whose partial blocks
 // k_spread_reduce sums.
+//
+// Batch record of one entry: W z weights, K complex values, then the W x
+// and W y weights (read per lane).
 template <int W, int K>
 struct PullRec {
-  static constexpr int n = 1 + 3 * W + 2 * K;     // l0, weights, values
+  static constexpr int zw = 0;                     // z weights
+  static constexpr int val = W;                    // values (re, im) x K
+  static constexpr int xw = W + 2 * K;             // x weights
+  static constexpr int yw = xw + W;                // y weights
+  static constexpr int n = yw + W;
   static constexpr int stride = (n + 3) & ~3;      // whole float4s
 };
 
+struct PullLane {
+  int gx, gy;          // the lane's column
+  bool inside;         // column inside the grid
+  int nfx, nfy;
+};
+
+// Entries v0 .. v1-1 of the batch, all with z offset D: node az of an entry
+// lands in register slot D + az (kept when inside the block's 8).
+template <int W, int K, int D>
+__device__ __forceinline__ void pull_run(const float *bf, int v0, int v1, int l0_lane,
+                                         const PullLane &pl, float (&ar)[kSB][K],
+                                         float (&ai)[kSB][K]) {
+  using R = PullRec<W, K>;
+  constexpr int RS = R::stride;
+#pragma unroll 1
+  for (int v = v0; v < v1; ++v) {
+    const float *pr = bf + v * RS;
+    const unsigned u = (unsigned)__builtin_amdgcn_readlane(l0_lane, v);
+    int dx = pl.gx - (int)(u & 1023u), dy = pl.gy - (int)((u >> 10) & 1023u);
+    dx += dx < 0 ? pl.nfx : 0;
+    dy += dy < 0 ? pl.nfy : 0;
+    const bool on = pl.inside && dx < W && dy < W;
+    const float wx = pr[R::xw + min(dx, W - 1)];
+    const float wy = pr[R::yw + min(dy, W - 1)];
+    const float wxy = on ? wx * wy : 0.f;
+#pragma unroll
+    for (int az = 0; az < W; ++az) {
+      if (D + az >= 0 && D + az < kSB) {
+        const float w = wxy * pr[R::zw + az];
+#pragma unroll
+        for (int kk = 0; kk < K; ++kk) {
+          ar[D + az][kk] = fmaf(w, pr[R::val + 2 * kk], ar[D + az][kk]);
+          ai[D + az][kk] = fmaf(w, pr[R::val + 2 * kk + 1], ai[D + az][kk]);
+        }
+      }
+    }
+  }
+}
+
 template <int W, bool MIX, int K>
 __global__ void __launch_bounds__(64) k_spread(SpreadDev a) {
-  constexpr int RS = PullRec<W, K>::stride;
+  static_assert(W <= 8 && kSB == 8 && kVisitOffsets == 16, "offset cases cover -7 .. 7");
+  using R = PullRec<W, K>;
+  constexpr int RS = R::stride;
   __shared__ float4 batch[64 * RS / 4];
   float *bf = reinterpret_cast<float *>(batch);
   const int4 it = a.items[blockIdx.x];
@@ -221,9 +271,12 @@ __global__ void __launch_bounds__(64) k_spread(SpreadDev a) {
   const int rem = it.x - bzi * (a.nbx * a.nby);
   const int byi = rem / a.nbx, bxi = rem - byi * a.nbx;
   const int ox = bxi * kSB, oy = byi * kSB, oz = bzi * kSB;
-  const int cx = lane & (kSB - 1), cy = lane / kSB;
-  const int gx = ox + cx, gy = oy + cy;
-  const bool inside = gx < a.nfx && gy < a.nfy;
+  PullLane pl;
+  pl.gx = ox + (lane & (kSB - 1));
+  pl.gy = oy + lane / kSB;
+  pl.inside = pl.gx < a.nfx && pl.gy < a.nfy;
+  pl.nfx = a.nfx;
+  pl.nfy = a.nfy;
 
   float ar[kSB][K], ai[kSB][K];
 #pragma unroll
@@ -233,83 +286,61 @@ __global__ void __launch_bounds__(64) k_spread(SpreadDev a) {
 
   for (int b0 = 0; b0 < it.z; b0 += 64) {
     const int nb = min(64, it.z - b0);
-    // fetch: lane L loads point b0 + L of the list
+    // fetch: lane L loads entry b0 + L of the list
+    int l0_lane = 0, d_lane = 0;
     if (lane < nb) {
-      const int j = a.vlist[it.y + b0 + lane];
+      const int raw = a.vlist[it.y + b0 + lane];
+      const int j = raw < 0 ? ~raw : raw;
       const float4 r = a.rec[j];
       const int2 id = a.pidx[j];
       const float *w = a.wts + (size_t)j * 3 * W;
       float *o = bf + lane * RS;
-      o[0] = r.w;
+      l0_lane = __float_as_int(r.w);
+      int e = (int)((__float_as_uint(r.w) >> 20) & 1023u) - oz;
+      e += e < 0 ? a.nfz : 0;
+      d_lane = raw < 0 ? e - a.nfz : e;
 #pragma unroll
-      for (int i = 0; i < 3 * W; ++i) o[1 + i] = w[i];
+      for (int i = 0; i < W; ++i) {
+        o[R::xw + i] = w[i];
+        o[R::yw + i] = w[W + i];
+        o[R::zw + i] = w[2 * W + i];
+      }
       const int col = a.src_plan ? j : id.y;
       if constexpr (MIX) {
         const float2 rv = a.src[(size_t)grp * a.M + col];
 #pragma unroll
         for (int kk = 0; kk < K; ++kk) {
           const float2 v = cmulc(rv, a.V[(size_t)id.x * K + kk]);
-          o[1 + 3 * W + 2 * kk] = v.x;
-          o[2 + 3 * W + 2 * kk] = v.y;
+          o[R::val + 2 * kk] = v.x;
+          o[R::val + 2 * kk + 1] = v.y;
         }
       } else {
 #pragma unroll
         for (int kk = 0; kk < K; ++kk) {
           const float2 v = a.src[(size_t)(grp * K + kk) * a.M + col];
-          o[1 + 3 * W + 2 * kk] = v.x;
-          o[2 + 3 * W + 2 * kk] = v.y;
+          o[R::val + 2 * kk] = v.x;
+          o[R::val + 2 * kk + 1] = v.y;
         }
       }
     }
+    // a batch is a piece of a list sorted by offset, so the entries of one
+    // offset form one run and the runs come in increasing offset order
     __syncthreads();
-    // walk: every lane reads point v of the batch
-    for (int v = 0; v < nb; ++v) {
-      float rr[RS];
-#pragma unroll
-      for (int q = 0; q < RS / 4; ++q) {
-        const float4 t = batch[v * (RS / 4) + q];
-        rr[4 * q] = t.x;
-        rr[4 * q + 1] = t.y;
-        rr[4 * q + 2] = t.z;
-        rr[4 * q + 3] = t.w;
-      }
-      // the point is the same for every lane: keep its nodes in scalar
-      // registers so that the z branch below is a scalar branch
-      int l0x, l0y, l0z;
-      unpack_l0(__int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(rr[0]))), l0x, l0y, l0z);
-      int dx = gx - l0x, dy = gy - l0y;
-      dx += dx < 0 ? a.nfx : 0;
-      dy += dy < 0 ? a.nfy : 0;
-      float wxl = 0.f, wyl = 0.f;
-#pragma unroll
-      for (int i = 0; i < W; ++i) {
-        wxl = dx == i ? rr[1 + i] : wxl;
-        wyl = dy == i ? rr[1 + W + i] : wyl;
-      }
-      const float wxy = inside ? wxl * wyl : 0.f;
-#pragma unroll
-      for (int az = 0; az < W; ++az) {
-        int zz = l0z + az;
-        zz -= zz >= a.nfz ? a.nfz : 0;
-        zz -= oz;
-        const float wz = wxy * rr[1 + 2 * W + az];
-        switch (zz) {
-#define SDN_ZCASE(C)                                                          \
-  case C:                                                                     \
-    _Pragma("unroll") for (int kk = 0; kk < K; ++kk) {                        \
-      ar[C][kk] = fmaf(wz, rr[1 + 3 * W + 2 * kk], ar[C][kk]);                \
-      ai[C][kk] = fmaf(wz, rr[2 + 3 * W + 2 * kk], ai[C][kk]);                \
-    }                                                                         \
-    break;
-          SDN_ZCASE(0) SDN_ZCASE(1) SDN_ZCASE(2) SDN_ZCASE(3)
-          SDN_ZCASE(4) SDN_ZCASE(5) SDN_ZCASE(6) SDN_ZCASE(7)
-#undef SDN_ZCASE
-          default: break;
-        }
-      }
-    }
+#define SDN_DRUN(D)                                                             \
+  {                                                                             \
+    const unsigned long long m = __ballot(lane < nb && d_lane == D);            \
+    if (m) {                                                                    \
+      const int v0 = (int)__builtin_ctzll(m);                                   \
+      pull_run<W, K, D>(bf, v0, v0 + (int)__builtin_popcountll(m), l0_lane, pl, ar, ai); \
+    }                                                                           \
+  }
+    SDN_DRUN(-7) SDN_DRUN(-6) SDN_DRUN(-5) SDN_DRUN(-4) SDN_DRUN(-3)
+    SDN_DRUN(-2) SDN_DRUN(-1) SDN_DRUN(0) SDN_DRUN(1) SDN_DRUN(2)
+    SDN_DRUN(3) SDN_DRUN(4) SDN_DRUN(5) SDN_DRUN(6) SDN_DRUN(7)
+#undef SDN_DRUN
     __syncthreads();
   }
+  const int gx = pl.gx, gy = pl.gy;
   if (it.w >= 0) {
     float2 *pp = a.part + ((size_t)it.w * a.groups + grp) * K * kSBCells;
 #pragma unroll
@@ -319,7 +350,7 @@ __global__ void __launch_bounds__(64) k_spread(SpreadDev a) {
         pp[(size_t)kk * kSBCells + c * 64 + lane] = make_float2(ar[c][kk], ai[c][kk]);
     return;
   }
-  if (!inside) return;
+  if (!pl.inside) return;
 #pragma unroll
   for (int kk = 0; kk < K; ++kk) {
     float2 *gp = a.grid + (size_t)(grp * K + kk) * a.G;

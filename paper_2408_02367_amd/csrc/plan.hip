@@ -1,6 +1,11 @@
 // Plan construction: fold and quantise the trajectory, bin the points into
-// fine-grid tiles and sort them tile by tile (a counting sort: histogram,
-// exclusive scan, scatter), then split crowded tiles into work items.
+// fine-grid tiles and sort them tile by tile, then split crowded tiles into
+// work items; build the spreading lists of the 8 x 8 x 8 blocks.
+//
+// Both sorts are stable radix sorts keyed by bin (the points in original
+// order within a tile, the list entries in plan order within a block and
+// z offset), so a plan, and with it every summation order of the grid
+// kernels, depends on the trajectory only.
 //
 // The trajectory of an MRF scan is fixed for every data-consistency step of
 // the reconstruction (Sec. 3: thousands of iterations over one scan), so
@@ -8,6 +13,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+
+#include <hipcub/hipcub.hpp>
 
 #include "nodes.h"
 #include "sdn_internal.h"
@@ -76,16 +83,20 @@ __global__ void k_fold(const float *__restrict__ traj, int M, FoldGeom g,
   atomicAdd(&count[kk], 1);
 }
 
-__global__ void k_scatter(const int *__restrict__ key, const float4 *__restrict__ rec_tmp,
-                          const int32_t *__restrict__ frame, int M,
-                          const int *__restrict__ offset, int *__restrict__ cursor,
-                          float4 *__restrict__ rec, int2 *__restrict__ pidx) {
+__global__ void k_iota(int *__restrict__ v, int M) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= M) return;
-  const int k = key[j];
-  const int pos = offset[k] + atomicAdd(&cursor[k], 1);
-  rec[pos] = rec_tmp[j];
-  pidx[pos] = make_int2(frame ? frame[j] : 0, j);
+  if (j < M) v[j] = j;
+}
+
+// Plan order: position i holds the point the sort placed there.
+__global__ void k_gather(const int *__restrict__ order, const float4 *__restrict__ rec_tmp,
+                         const int32_t *__restrict__ frame, int M,
+                         float4 *__restrict__ rec, int2 *__restrict__ pidx) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M) return;
+  const int j = order[i];
+  rec[i] = rec_tmp[j];
+  pidx[i] = make_int2(frame ? frame[j] : 0, j);
 }
 
 // Tiles of one axis touched by the W nodes l0 .. l0+W-1 (mod nf), in order.
@@ -104,27 +115,121 @@ __device__ __forceinline__ int axis_tiles(int l0, int W, int nf, int b, int (&t)
   return n;
 }
 
-// Spreading lists: for every tile, the points whose kernel support touches
-// it (a point is listed under up to 2 tiles per axis when tiles are at
-// least W-1 cells wide).  Pass 1 counts, pass 2 scatters plan indices.
-__global__ void k_visit(const float4 *__restrict__ rec, int M, FoldGeom g,
-                        const int *__restrict__ offset, int *__restrict__ cursor,
-                        int *__restrict__ list) {
+// Spreading-list entries of one point.  Along x and y a point is listed
+// under every block its W nodes touch.  Along z the entry also fixes the
+// offset d of the first node against the block (register slot c = d + az
+// for node az): d = e or d = e - nf with e = (l0 - oz) mod nf, whichever
+// puts a node inside the block; on grids shorter than a block plus the
+// kernel both can (a support that wraps onto both ends of the block), and
+// the point is listed twice, once per side, each entry covering its own
+// nodes.  Entries for the second form carry the complemented index.
+struct VisitZ {
+  int n;
+  int blk[4];
+  int d[4];
+  bool neg[4];
+};
+
+__device__ __forceinline__ void visit_z(int l0, int W, int nf, VisitZ &v) {
+  int t[8];
+  const int nt = axis_tiles(l0, W, nf, kSpreadBlock, t);
+  v.n = 0;
+  for (int a = 0; a < nt; ++a) {
+    const int oz = t[a] * kSpreadBlock;
+    const int bw = min(kSpreadBlock, nf - oz);
+    int e = l0 - oz;
+    e += e < 0 ? nf : 0;
+    if (e < bw) {
+      v.blk[v.n] = t[a];
+      v.d[v.n] = e;
+      v.neg[v.n++] = false;
+    }
+    if (e - nf > -W) {
+      v.blk[v.n] = t[a];
+      v.d[v.n] = e - nf;
+      v.neg[v.n++] = true;
+    }
+  }
+}
+
+// Pass 1: entries per point and per block.
+__global__ void k_visit_count(const float4 *__restrict__ rec, int M, FoldGeom g,
+                              int *__restrict__ per_block, int *__restrict__ per_point) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= M) return;
   const unsigned u = __float_as_uint(rec[j].w);
-  const int l0[3] = {(int)(u & 1023u), (int)((u >> 10) & 1023u), (int)((u >> 20) & 1023u)};
-  int tx[8], ty[8], tz[8];
-  const int nx = axis_tiles(l0[0], g.W, g.nf[0], g.tile[0], tx);
-  const int ny = axis_tiles(l0[1], g.W, g.nf[1], g.tile[1], ty);
-  const int nz = axis_tiles(l0[2], g.W, g.nf[2], g.tile[2], tz);
-  for (int a = 0; a < nz; ++a)
+  int tx[8], ty[8];
+  const int nx = axis_tiles((int)(u & 1023u), g.W, g.nf[0], kSpreadBlock, tx);
+  const int ny = axis_tiles((int)((u >> 10) & 1023u), g.W, g.nf[1], kSpreadBlock, ty);
+  VisitZ vz;
+  visit_z((int)((u >> 20) & 1023u), g.W, g.nf[2], vz);
+  for (int a = 0; a < vz.n; ++a)
+    for (int c = 0; c < ny; ++c)
+      for (int i = 0; i < nx; ++i)
+        atomicAdd(&per_block[(vz.blk[a] * g.ntile[1] + ty[c]) * g.ntile[0] + tx[i]], 1);
+  per_point[j] = vz.n * ny * nx;
+}
+
+// Pass 2: (block, offset) key and entry of every visit, at the point's
+// position of the exclusive scan of pass 1 (so in plan order).
+__global__ void k_visit_pairs(const float4 *__restrict__ rec, int M, FoldGeom g,
+                              const int *__restrict__ pos, unsigned *__restrict__ key,
+                              int *__restrict__ val) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= M) return;
+  const unsigned u = __float_as_uint(rec[j].w);
+  int tx[8], ty[8];
+  const int nx = axis_tiles((int)(u & 1023u), g.W, g.nf[0], kSpreadBlock, tx);
+  const int ny = axis_tiles((int)((u >> 10) & 1023u), g.W, g.nf[1], kSpreadBlock, ty);
+  VisitZ vz;
+  visit_z((int)((u >> 20) & 1023u), g.W, g.nf[2], vz);
+  int o = pos[j];
+  for (int a = 0; a < vz.n; ++a)
     for (int c = 0; c < ny; ++c)
       for (int i = 0; i < nx; ++i) {
-        const int key = (tz[a] * g.ntile[1] + ty[c]) * g.ntile[0] + tx[i];
-        const int slot = atomicAdd(&cursor[key], 1);
-        if (list) list[offset[key] + slot] = j;
+        const unsigned blk = (unsigned)((vz.blk[a] * g.ntile[1] + ty[c]) * g.ntile[0] + tx[i]);
+        key[o] = blk * kVisitOffsets + (unsigned)(vz.d[a] + kVisitOffsets / 2 - 1);
+        val[o++] = vz.neg[a] ? ~j : j;
       }
+}
+
+int key_bits(uint64_t nkeys) {
+  int b = 1;
+  while (b < 32 && (1ull << b) < nkeys) ++b;
+  return b;
+}
+
+// Stable LSD radix sort of (key, value) pairs on the low `bits` key bits.
+template <typename KT>
+sdn_status sort_pairs(const KT *kin, KT *kout, const int *vin, int *vout, int n, int bits,
+                      hipStream_t st) {
+  size_t tmp_bytes = 0;
+  if (hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, kin, kout, vin, vout, n, 0, bits,
+                                         st) != hipSuccess)
+    return fail(SDN_E_HIP, "plan sort: temporary size query failed");
+  void *tmp = nullptr;
+  if (hipMalloc(&tmp, std::max<size_t>(tmp_bytes, 16)) != hipSuccess)
+    return fail(SDN_E_NOMEM, "plan sort: no device memory for the sort");
+  sdn_status s = hip_check(hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, kin, kout, vin,
+                                                              vout, n, 0, bits, st),
+                           "plan sort");
+  if (s == SDN_OK) s = hip_check(hipStreamSynchronize(st), "plan sync");
+  (void)hipFree(tmp);
+  return s;
+}
+
+sdn_status exclusive_sum(const int *in, int *out, int n, hipStream_t st) {
+  size_t tmp_bytes = 0;
+  if (hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_bytes, in, out, n, st) != hipSuccess)
+    return fail(SDN_E_HIP, "plan scan: temporary size query failed");
+  void *tmp = nullptr;
+  if (hipMalloc(&tmp, std::max<size_t>(tmp_bytes, 16)) != hipSuccess)
+    return fail(SDN_E_NOMEM, "plan scan: no device memory for the scan");
+  sdn_status s = hip_check(hipcub::DeviceScan::ExclusiveSum(tmp, tmp_bytes, in, out, n, st),
+                           "plan scan");
+  if (s == SDN_OK) s = hip_check(hipStreamSynchronize(st), "plan sync");
+  (void)hipFree(tmp);
+  return s;
 }
 
 // Kernel weights of every point (plan order), evaluated once per plan with
@@ -296,18 +401,22 @@ sdn_status sdn_plan_create(sdn_plan *out, const int64_t shape[3], const float *t
   p->nbins = (int64_t)p->ax[0].ntile * p->ax[1].ntile * p->ax[2].ntile;
   p->nsbins = (int64_t)p->ax[0].nsblk * p->ax[1].nsblk * p->ax[2].nsblk;
 
-  int *key = nullptr, *count = nullptr, *cursor = nullptr, *offset = nullptr, *bad = nullptr;
+  // scratch of the two sorts, freed before returning
+  int *key = nullptr, *key2 = nullptr, *ord_in = nullptr, *ord = nullptr, *count = nullptr;
+  int *bad = nullptr, *npv = nullptr, *ppos = nullptr, *vval = nullptr;
+  unsigned *vkey = nullptr, *vkey2 = nullptr;
   float4 *rec_tmp = nullptr;
   if (s == SDN_OK && M > 0) {
     const int m = (int)M;
     const int nb = (int)p->nbins;
     const int nsb = (int)p->nsbins;
-    const int nbmax = std::max(nb, nsb);
+    const dim3 grd((m + 255) / 256);
     s = dalloc(&key, m, "plan sort");
+    if (s == SDN_OK) s = dalloc(&key2, m, "plan sort");
+    if (s == SDN_OK) s = dalloc(&ord_in, m, "plan sort");
+    if (s == SDN_OK) s = dalloc(&ord, m, "plan sort");
     if (s == SDN_OK) s = dalloc(&rec_tmp, m, "plan sort");
-    if (s == SDN_OK) s = dalloc(&count, nb, "plan sort");
-    if (s == SDN_OK) s = dalloc(&cursor, nbmax, "plan sort");
-    if (s == SDN_OK) s = dalloc(&offset, nbmax, "plan sort");
+    if (s == SDN_OK) s = dalloc(&count, std::max(nb, nsb), "plan sort");
     if (s == SDN_OK) s = dalloc(&bad, 1, "plan sort");
     if (s == SDN_OK) s = dalloc(&p->rec, m, "plan points");
     if (s == SDN_OK) s = dalloc(&p->pidx, m, "plan points");
@@ -319,7 +428,6 @@ sdn_status sdn_plan_create(sdn_plan *out, const int64_t shape[3], const float *t
                       "plan frame copy");
     }
     if (s == SDN_OK) s = hip_check(hipMemsetAsync(count, 0, (size_t)nb * 4, st), "plan memset");
-    if (s == SDN_OK) s = hip_check(hipMemsetAsync(cursor, 0, (size_t)nb * 4, st), "plan memset");
     if (s == SDN_OK) s = hip_check(hipMemsetAsync(bad, 0, 4, st), "plan memset");
     FoldGeom g;
     for (int d = 0; d < 3; ++d) {
@@ -330,8 +438,9 @@ sdn_status sdn_plan_create(sdn_plan *out, const int64_t shape[3], const float *t
     g.W = p->W;
     g.T = p->T;
     if (s == SDN_OK) {
-      hipLaunchKernelGGL(k_fold, dim3((m + 255) / 256), dim3(256), 0, st, traj, m, g,
-                         frame_of_point, key, rec_tmp, count, bad);
+      hipLaunchKernelGGL(k_fold, grd, dim3(256), 0, st, traj, m, g, frame_of_point, key, rec_tmp,
+                         count, bad);
+      hipLaunchKernelGGL(k_iota, grd, dim3(256), 0, st, ord_in, m);
       s = hip_check(hipGetLastError(), "plan fold kernel");
     }
     std::vector<int> hcount(nb);
@@ -346,13 +455,12 @@ sdn_status sdn_plan_create(sdn_plan *out, const int64_t shape[3], const float *t
       s = fail(SDN_E_RANGE, "sdn_plan_create: non-finite coordinate or |k| > 2^20");
     if (s == SDN_OK && (hbad & 2))
       s = fail(SDN_E_RANGE, "sdn_plan_create: frame_of_point outside [0, T)");
-    std::vector<int> hoff(nb);
-    std::vector<int4> items;
+    // interpolation items: the points of a tile, crowded tiles split
     if (s == SDN_OK) {
+      std::vector<int4> items;
       int64_t acc = 0;
       const int cap = p->max_points_per_item;
       for (int b = 0; b < nb; ++b) {
-        hoff[b] = (int)acc;
         const int c = hcount[b];
         p->max_bin = std::max<int64_t>(p->max_bin, c);
         for (int st0 = 0; st0 < c; st0 += cap)
@@ -364,23 +472,23 @@ sdn_status sdn_plan_create(sdn_plan *out, const int64_t shape[3], const float *t
                        [](const int4 &a, const int4 &b) { return a.z > b.z; });
       p->nwork = (int64_t)items.size();
       s = dalloc(&p->work, items.size(), "plan work list");
-      if (s == SDN_OK)
-        s = hip_check(hipMemcpyAsync(offset, hoff.data(), (size_t)nb * 4, hipMemcpyHostToDevice, st),
-                      "plan offsets upload");
       if (s == SDN_OK && !items.empty())
         s = hip_check(hipMemcpyAsync(p->work, items.data(), items.size() * sizeof(int4),
                                      hipMemcpyHostToDevice, st),
                       "plan work upload");
     }
+    // plan order: points sorted by tile, original order within a tile
+    if (s == SDN_OK)
+      s = sort_pairs(reinterpret_cast<const unsigned *>(key), reinterpret_cast<unsigned *>(key2),
+                     ord_in, ord, m, key_bits((uint64_t)nb), st);
     if (s == SDN_OK) {
-      hipLaunchKernelGGL(k_scatter, dim3((m + 255) / 256), dim3(256), 0, st, key, rec_tmp,
-                         frame_of_point, m, offset, cursor, p->rec, p->pidx);
-      s = hip_check(hipGetLastError(), "plan scatter kernel");
+      hipLaunchKernelGGL(k_gather, grd, dim3(256), 0, st, ord, rec_tmp, frame_of_point, m, p->rec,
+                         p->pidx);
+      s = hip_check(hipGetLastError(), "plan gather kernel");
     }
     // per-point kernel weights
     if (s == SDN_OK) s = dalloc(&p->wts, (size_t)m * 3 * p->W, "plan weights");
     if (s == SDN_OK) {
-      const dim3 grd((m + 255) / 256);
       if (p->W == 4)
         hipLaunchKernelGGL((k_weights<4, 8>), grd, dim3(256), 0, st, p->rec, m, p->coef, p->wts);
       else if (p->W == 8)
@@ -389,32 +497,32 @@ sdn_status sdn_plan_create(sdn_plan *out, const int64_t shape[3], const float *t
         hipLaunchKernelGGL((k_weights<6, 10>), grd, dim3(256), 0, st, p->rec, m, p->coef, p->wts);
       s = hip_check(hipGetLastError(), "plan weights kernel");
     }
-    // spreading lists over the sorted points and the spreading blocks:
-    // count, scan, scatter
+    // spreading lists: entries per block and per point, scan, (block,
+    // offset)-keyed pairs in plan order, stable sort
     FoldGeom gs = g;
     for (int d = 0; d < 3; ++d) {
       gs.tile[d] = p->ax[d].sblk;
       gs.ntile[d] = p->ax[d].nsblk;
     }
-    std::vector<int> scount(nsb), soff(nsb);
-    if (s == SDN_OK) s = hip_check(hipMemsetAsync(cursor, 0, (size_t)nsb * 4, st), "plan memset");
+    std::vector<int> scount(nsb);
+    if (s == SDN_OK) s = dalloc(&npv, m, "plan spreading lists");
+    if (s == SDN_OK) s = dalloc(&ppos, m, "plan spreading lists");
+    if (s == SDN_OK) s = hip_check(hipMemsetAsync(count, 0, (size_t)nsb * 4, st), "plan memset");
     if (s == SDN_OK) {
-      hipLaunchKernelGGL(k_visit, dim3((m + 255) / 256), dim3(256), 0, st, p->rec, m, gs,
-                         offset, cursor, (int *)nullptr);
+      hipLaunchKernelGGL(k_visit_count, grd, dim3(256), 0, st, p->rec, m, gs, count, npv);
       s = hip_check(hipGetLastError(), "plan visit count kernel");
     }
     if (s == SDN_OK)
-      s = hip_check(hipMemcpyAsync(scount.data(), cursor, (size_t)nsb * 4, hipMemcpyDeviceToHost, st),
+      s = hip_check(hipMemcpyAsync(scount.data(), count, (size_t)nsb * 4, hipMemcpyDeviceToHost, st),
                     "plan visit download");
     if (s == SDN_OK) s = hip_check(hipStreamSynchronize(st), "plan sync");
     // spreading items: one per block (blocks without points still write
     // their zeros); a crowded block is split into several items whose
     // partial blocks are summed afterwards
-    std::vector<int4> sitems, splits;
     if (s == SDN_OK) {
+      std::vector<int4> sitems, splits;
       int64_t acc = 0, slot = 0;
       for (int b = 0; b < nsb; ++b) {
-        soff[b] = (int)acc;
         const int c = scount[b];
         const int nch = std::max(1, (c + kSpreadCap - 1) / kSpreadCap);
         if (nch == 1) {
@@ -426,6 +534,7 @@ sdn_status sdn_plan_create(sdn_plan *out, const int64_t shape[3], const float *t
                                        std::min(kSpreadCap, c - q * kSpreadCap), (int)slot++));
         }
         acc += c;
+        if (acc > INT32_MAX - 1024) break;
       }
       if (acc > INT32_MAX - 1024) s = fail(SDN_E_UNSUPPORTED, "sdn_plan_create: too many points");
       p->nvisit = acc;
@@ -434,29 +543,35 @@ sdn_status sdn_plan_create(sdn_plan *out, const int64_t shape[3], const float *t
                        [](const int4 &a, const int4 &b) { return a.z > b.z; });
       p->nsitems = (int64_t)sitems.size();
       p->nsplit = (int64_t)splits.size();
+      if (s == SDN_OK) s = dalloc(&p->sitems, sitems.size(), "plan spreading items");
+      if (s == SDN_OK) s = dalloc(&p->splits, splits.size(), "plan spreading items");
+      if (s == SDN_OK)
+        s = hip_check(hipMemcpyAsync(p->sitems, sitems.data(), sitems.size() * sizeof(int4),
+                                     hipMemcpyHostToDevice, st), "plan items upload");
+      if (s == SDN_OK && !splits.empty())
+        s = hip_check(hipMemcpyAsync(p->splits, splits.data(), splits.size() * sizeof(int4),
+                                     hipMemcpyHostToDevice, st), "plan items upload");
     }
-    if (s == SDN_OK) s = dalloc(&p->vlist, (size_t)p->nvisit, "plan spreading lists");
-    if (s == SDN_OK) s = dalloc(&p->sitems, sitems.size(), "plan spreading items");
-    if (s == SDN_OK) s = dalloc(&p->splits, splits.size(), "plan spreading items");
-    if (s == SDN_OK)
-      s = hip_check(hipMemcpyAsync(p->sitems, sitems.data(), sitems.size() * sizeof(int4),
-                                   hipMemcpyHostToDevice, st), "plan items upload");
-    if (s == SDN_OK && !splits.empty())
-      s = hip_check(hipMemcpyAsync(p->splits, splits.data(), splits.size() * sizeof(int4),
-                                   hipMemcpyHostToDevice, st), "plan items upload");
-    if (s == SDN_OK)
-      s = hip_check(hipMemcpyAsync(offset, soff.data(), (size_t)nsb * 4, hipMemcpyHostToDevice, st),
-                    "plan lists upload");
-    if (s == SDN_OK) s = hip_check(hipMemsetAsync(cursor, 0, (size_t)nsb * 4, st), "plan memset");
-    if (s == SDN_OK && p->nvisit > 0) {
-      hipLaunchKernelGGL(k_visit, dim3((m + 255) / 256), dim3(256), 0, st, p->rec, m, gs,
-                         offset, cursor, p->vlist);
-      s = hip_check(hipGetLastError(), "plan visit scatter kernel");
+    const int nv = (int)p->nvisit;
+    if (s == SDN_OK) s = dalloc(&p->vlist, (size_t)std::max(nv, 1), "plan spreading lists");
+    if (s == SDN_OK && nv > 0) {
+      s = exclusive_sum(npv, ppos, m, st);
+      if (s == SDN_OK) s = dalloc(&vkey, nv, "plan spreading lists");
+      if (s == SDN_OK) s = dalloc(&vkey2, nv, "plan spreading lists");
+      if (s == SDN_OK) s = dalloc(&vval, nv, "plan spreading lists");
+      if (s == SDN_OK) {
+        hipLaunchKernelGGL(k_visit_pairs, grd, dim3(256), 0, st, p->rec, m, gs, ppos, vkey, vval);
+        s = hip_check(hipGetLastError(), "plan visit pairs kernel");
+      }
+      if (s == SDN_OK)
+        s = sort_pairs(vkey, vkey2, vval, p->vlist, nv,
+                       key_bits((uint64_t)nsb * kVisitOffsets), st);
     }
     if (s == SDN_OK) s = hip_check(hipStreamSynchronize(st), "plan sync");
   }
-  for (void *q : {(void *)key, (void *)rec_tmp, (void *)count, (void *)cursor, (void *)offset,
-                  (void *)bad})
+  for (void *q : {(void *)key, (void *)key2, (void *)ord_in, (void *)ord, (void *)rec_tmp,
+                  (void *)count, (void *)bad, (void *)npv, (void *)ppos, (void *)vkey,
+                  (void *)vkey2, (void *)vval})
     if (q) (void)hipFree(q);
   if (s != SDN_OK) {
     free_plan_memory(p);

@@ -50,6 +50,7 @@ struct Axis {
 };
 
 constexpr int kSpreadBlock = 8;   // spreading blocks are 8 x 8 x 8 fine cells
+constexpr int kVisitOffsets = 16; // z offsets -7 .. 7 of a list entry, one key slot each
 
 // Every status-returning path records a message through this.
 sdn_status fail(sdn_status s, const std::string &msg);

@@ -55,6 +55,7 @@ TileGeom tile_geom(const sdn_plan_s &p) {
 struct InterpDev {
   const float4 *rec;
   const int2 *pidx;
+  const float *wts;    // per point: W weights for x, y, z
   const int4 *work;
   int M;
   TileGeom g;
@@ -71,14 +72,16 @@ struct InterpDev {
 
 constexpr int kThreads = 256;
 constexpr int kIThreads = 512;                // interpolation workgroup
-constexpr int kPPT = kItemCap / kIThreads;    // points per thread per item
 
 // grid = (items, groups).  Mix mode: a group is one coil and its K channels,
 // output y_b = sum_k V[t][k] u_k (+ DC epilogue), the running sums kept in
 // LDS behind the staged tile.  Otherwise a group is K independent channels
-// with outputs y_{gK+k} = u_k.
-template <int W, int NC, bool MIX, bool DC>
-__global__ void __launch_bounds__(kIThreads) k_interp(InterpDev a, KerCoef kc) {
+// with outputs y_{gK+k} = u_k.  The plan orders the points of a tile so
+// that every 16 consecutive points start at tile cells of distinct residues
+// mod 16; each 16-lane group's 8-byte LDS reads then hit distinct banks at
+// every one of the W^3 offsets.
+template <int W, bool MIX, bool DC>
+__global__ void __launch_bounds__(kIThreads) k_interp(InterpDev a) {
   extern __shared__ float2 tile[];
   const TileGeom &g = a.g;
   const int4 wi = a.work[blockIdx.x];
@@ -108,15 +111,20 @@ __global__ void __launch_bounds__(kIThreads) k_interp(InterpDev a, KerCoef kc) {
     __syncthreads();
 #pragma unroll 1
     for (int q = tid; q < wi.z; q += kIThreads) {
-      const float4 rc = a.rec[wi.y + q];
       const int2 id = a.pidx[wi.y + q];
       int lx, ly, lz;
-      unpack_l0(rc.w, lx, ly, lz);
+      unpack_l0(a.rec[wi.y + q].w, lx, ly, lz);
       lx -= ox; ly -= oy; lz -= oz;
+      static_assert((3 * W) % 2 == 0, "weights are read as float2");
+      const float2 *wp = reinterpret_cast<const float2 *>(a.wts + (size_t)(wi.y + q) * 3 * W);
       float wx[W], wy[W], wz[W];
-      axis_weights<W, NC>(rc.x, kc, wx);
-      axis_weights<W, NC>(rc.y, kc, wy);
-      axis_weights<W, NC>(rc.z, kc, wz);
+#pragma unroll
+      for (int i = 0; i < 3 * W / 2; ++i) {
+        const float2 t = wp[i];
+        const int e0 = 2 * i, e1 = 2 * i + 1;
+        (e0 < W ? wx[e0] : e0 < 2 * W ? wy[e0 - W] : wz[e0 - 2 * W]) = t.x;
+        (e1 < W ? wx[e1] : e1 < 2 * W ? wy[e1 - W] : wz[e1 - 2 * W]) = t.y;
+      }
       float ur = 0.f, ui = 0.f;
 #pragma unroll
       for (int az = 0; az < W; ++az) {
@@ -428,20 +436,20 @@ namespace {
 template <typename F>
 hipError_t allow_lds_fwd(F *kernel, size_t bytes);
 
-template <int W, int NC, bool MIX, bool DC>
-hipError_t interp_one(const InterpDev &d, const KerCoef &kc, dim3 grd, size_t lds, hipStream_t st) {
-  hipError_t e = allow_lds_fwd(k_interp<W, NC, MIX, DC>, lds);
+template <int W, bool MIX, bool DC>
+hipError_t interp_one(const InterpDev &d, dim3 grd, size_t lds, hipStream_t st) {
+  hipError_t e = allow_lds_fwd(k_interp<W, MIX, DC>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_interp<W, NC, MIX, DC>), grd, dim3(kIThreads), lds, st, d, kc);
+  hipLaunchKernelGGL((k_interp<W, MIX, DC>), grd, dim3(kIThreads), lds, st, d);
   return hipGetLastError();
 }
 
-template <int W, int NC>
-hipError_t interp_launch(const InterpDev &d, const KerCoef &kc, bool mix, bool dc, dim3 grd,
-                         size_t lds, hipStream_t st) {
-  if (mix && dc) return interp_one<W, NC, true, true>(d, kc, grd, lds, st);
-  if (mix) return interp_one<W, NC, true, false>(d, kc, grd, lds, st);
-  return interp_one<W, NC, false, false>(d, kc, grd, lds, st);
+template <int W>
+hipError_t interp_launch(const InterpDev &d, bool mix, bool dc, dim3 grd, size_t lds,
+                         hipStream_t st) {
+  if (mix && dc) return interp_one<W, true, true>(d, grd, lds, st);
+  if (mix) return interp_one<W, true, false>(d, grd, lds, st);
+  return interp_one<W, false, false>(d, grd, lds, st);
 }
 
 }  // namespace
@@ -480,6 +488,7 @@ hipError_t launch_interp(const sdn_plan_s &p, const InterpArgs &a, hipStream_t s
   InterpDev d;
   d.rec = p.rec;
   d.pidx = p.pidx;
+  d.wts = p.wts;
   d.work = p.work;
   d.M = (int)p.M;
   d.g = tile_geom(p);
@@ -499,9 +508,9 @@ hipError_t launch_interp(const sdn_plan_s &p, const InterpArgs &a, hipStream_t s
   if (lds > max_lds_bytes()) return hipErrorInvalidValue;
   dim3 grd((unsigned)p.nwork, (unsigned)a.groups);
   switch (p.W) {
-    case 4: return interp_launch<4, 8>(d, p.coef, mix, dc, grd, lds, st);
-    case 8: return interp_launch<8, 12>(d, p.coef, mix, dc, grd, lds, st);
-    default: return interp_launch<6, 10>(d, p.coef, mix, dc, grd, lds, st);
+    case 4: return interp_launch<4>(d, mix, dc, grd, lds, st);
+    case 8: return interp_launch<8>(d, mix, dc, grd, lds, st);
+    default: return interp_launch<6>(d, mix, dc, grd, lds, st);
   }
 }
 

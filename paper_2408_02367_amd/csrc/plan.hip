@@ -2,10 +2,10 @@
 // fine-grid tiles and sort them tile by tile, then split crowded tiles into
 // work items; build the spreading lists of the 8 x 8 x 8 blocks.
 //
-// Both sorts are stable radix sorts keyed by bin (the points in original
-// order within a tile, the list entries in plan order within a block and
-// z offset), so a plan, and with it every summation order of the grid
-// kernels, depends on the trajectory only.
+// Both sorts are stable radix sorts keyed by bin (the points by tile and
+// LDS bank class, the list entries by block and z offset, each in a fixed
+// order within its bin), so a plan, and with it every summation order of
+// the grid kernels, depends on the trajectory only.
 //
 // The trajectory of an MRF scan is fixed for every data-consistency step of
 // the reconstruction (Sec. 3: thousands of iterations over one scan), so
@@ -36,6 +36,11 @@ struct FoldGeom {
   int W;
   int T;
 };
+
+// Residue classes of a point's first tile cell in the interpolation
+// kernel's LDS copy of the tile (pitches bx + W - 1 and by + W - 1, 8-byte
+// cells): 16 consecutive cells cover the 32 four-byte LDS banks once.
+constexpr int kBankClasses = 16;
 
 // One thread per point.  Fine coordinate s = k nf / (2 pi) in FP64; the W
 // nodes of the point are l0 .. l0+W-1 with l0 = floor(s - W/2) + 1 (the
@@ -71,16 +76,19 @@ __global__ void k_fold(const float *__restrict__ traj, int M, FoldGeom g,
   }
   if (!ok) {
     atomicOr(bad, 1);
-    key[j] = 0;
     l0[0] = l0[1] = l0[2] = 0;
     t[0] = t[1] = t[2] = 0.f;
   }
   const int tx = l0[0] / g.tile[0], ty = l0[1] / g.tile[1], tz = l0[2] / g.tile[2];
   const int kk = (tz * g.ntile[1] + ty) * g.ntile[0] + tx;
-  key[j] = kk;
+  const int px = g.tile[0] + g.W - 1, py = g.tile[1] + g.W - 1;
+  const int cell = ((l0[2] - tz * g.tile[2]) * py + (l0[1] - ty * g.tile[1])) * px +
+                   (l0[0] - tx * g.tile[0]);
+  const int kc = kk * kBankClasses + (cell & (kBankClasses - 1));
+  key[j] = kc;
   const unsigned packed = (unsigned)l0[0] | ((unsigned)l0[1] << 10) | ((unsigned)l0[2] << 20);
   rec[j] = make_float4(t[0], t[1], t[2], __uint_as_float(packed));
-  atomicAdd(&count[kk], 1);
+  atomicAdd(&count[kc], 1);
 }
 
 __global__ void k_iota(int *__restrict__ v, int M) {
@@ -88,15 +96,30 @@ __global__ void k_iota(int *__restrict__ v, int M) {
   if (j < M) v[j] = j;
 }
 
-// Plan order: position i holds the point the sort placed there.
-__global__ void k_gather(const int *__restrict__ order, const float4 *__restrict__ rec_tmp,
-                         const int32_t *__restrict__ frame, int M,
-                         float4 *__restrict__ rec, int2 *__restrict__ pidx) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= M) return;
-  const int j = order[i];
-  rec[i] = rec_tmp[j];
-  pidx[i] = make_int2(frame ? frame[j] : 0, j);
+// Plan order.  The sort leaves the points of a tile grouped by bank class
+// (original order within a class); the i-th point of class c then goes to
+// round i of a round-robin over the tile's classes:
+//   pos = sum_c' min(n_c', i) + #{c' < c : n_c' > i},
+// so that consecutive points mostly differ in class.
+__global__ void k_place(const unsigned *__restrict__ skey, const int *__restrict__ order,
+                        const float4 *__restrict__ rec_tmp, const int32_t *__restrict__ frame,
+                        int M, const int *__restrict__ tile_start,
+                        const int *__restrict__ class_count, float4 *__restrict__ rec,
+                        int2 *__restrict__ pidx) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= M) return;
+  const unsigned kv = skey[s];
+  const int t = (int)(kv / kBankClasses), c = (int)(kv % kBankClasses);
+  const int *n = class_count + (size_t)t * kBankClasses;
+  int before = 0;
+  for (int q = 0; q < c; ++q) before += n[q];
+  const int i = s - tile_start[t] - before;
+  int pos = 0;
+  for (int q = 0; q < kBankClasses; ++q) pos += min(n[q], i) + (q < c && n[q] > i ? 1 : 0);
+  const int dst = tile_start[t] + pos;
+  const int j = order[s];
+  rec[dst] = rec_tmp[j];
+  pidx[dst] = make_int2(frame ? frame[j] : 0, j);
 }
 
 // Tiles of one axis touched by the W nodes l0 .. l0+W-1 (mod nf), in order.
@@ -403,6 +426,7 @@ sdn_status sdn_plan_create(sdn_plan *out, const int64_t shape[3], const float *t
 
   // scratch of the two sorts, freed before returning
   int *key = nullptr, *key2 = nullptr, *ord_in = nullptr, *ord = nullptr, *count = nullptr;
+  int *ccount = nullptr, *tstart = nullptr;
   int *bad = nullptr, *npv = nullptr, *ppos = nullptr, *vval = nullptr;
   unsigned *vkey = nullptr, *vkey2 = nullptr;
   float4 *rec_tmp = nullptr;
@@ -416,7 +440,9 @@ sdn_status sdn_plan_create(sdn_plan *out, const int64_t shape[3], const float *t
     if (s == SDN_OK) s = dalloc(&ord_in, m, "plan sort");
     if (s == SDN_OK) s = dalloc(&ord, m, "plan sort");
     if (s == SDN_OK) s = dalloc(&rec_tmp, m, "plan sort");
-    if (s == SDN_OK) s = dalloc(&count, std::max(nb, nsb), "plan sort");
+    if (s == SDN_OK) s = dalloc(&ccount, (size_t)nb * kBankClasses, "plan sort");
+    if (s == SDN_OK) s = dalloc(&tstart, nb, "plan sort");
+    if (s == SDN_OK) s = dalloc(&count, nsb, "plan sort");
     if (s == SDN_OK) s = dalloc(&bad, 1, "plan sort");
     if (s == SDN_OK) s = dalloc(&p->rec, m, "plan points");
     if (s == SDN_OK) s = dalloc(&p->pidx, m, "plan points");
@@ -427,7 +453,8 @@ sdn_status sdn_plan_create(sdn_plan *out, const int64_t shape[3], const float *t
                                      hipMemcpyDeviceToDevice, st),
                       "plan frame copy");
     }
-    if (s == SDN_OK) s = hip_check(hipMemsetAsync(count, 0, (size_t)nb * 4, st), "plan memset");
+    if (s == SDN_OK)
+      s = hip_check(hipMemsetAsync(ccount, 0, (size_t)nb * kBankClasses * 4, st), "plan memset");
     if (s == SDN_OK) s = hip_check(hipMemsetAsync(bad, 0, 4, st), "plan memset");
     FoldGeom g;
     for (int d = 0; d < 3; ++d) {
@@ -439,14 +466,15 @@ sdn_status sdn_plan_create(sdn_plan *out, const int64_t shape[3], const float *t
     g.T = p->T;
     if (s == SDN_OK) {
       hipLaunchKernelGGL(k_fold, grd, dim3(256), 0, st, traj, m, g, frame_of_point, key, rec_tmp,
-                         count, bad);
+                         ccount, bad);
       hipLaunchKernelGGL(k_iota, grd, dim3(256), 0, st, ord_in, m);
       s = hip_check(hipGetLastError(), "plan fold kernel");
     }
-    std::vector<int> hcount(nb);
+    std::vector<int> hclass((size_t)nb * kBankClasses), hcount(nb), hstart(nb);
     int hbad = 0;
     if (s == SDN_OK)
-      s = hip_check(hipMemcpyAsync(hcount.data(), count, (size_t)nb * 4, hipMemcpyDeviceToHost, st),
+      s = hip_check(hipMemcpyAsync(hclass.data(), ccount, hclass.size() * 4, hipMemcpyDeviceToHost,
+                                   st),
                     "plan histogram download");
     if (s == SDN_OK)
       s = hip_check(hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, st), "plan flag download");
@@ -461,7 +489,10 @@ sdn_status sdn_plan_create(sdn_plan *out, const int64_t shape[3], const float *t
       int64_t acc = 0;
       const int cap = p->max_points_per_item;
       for (int b = 0; b < nb; ++b) {
-        const int c = hcount[b];
+        int c = 0;
+        for (int q = 0; q < kBankClasses; ++q) c += hclass[(size_t)b * kBankClasses + q];
+        hcount[b] = c;
+        hstart[b] = (int)acc;
         p->max_bin = std::max<int64_t>(p->max_bin, c);
         for (int st0 = 0; st0 < c; st0 += cap)
           items.push_back(make_int4(b, (int)acc + st0, std::min(cap, c - st0), 0));
@@ -476,15 +507,20 @@ sdn_status sdn_plan_create(sdn_plan *out, const int64_t shape[3], const float *t
         s = hip_check(hipMemcpyAsync(p->work, items.data(), items.size() * sizeof(int4),
                                      hipMemcpyHostToDevice, st),
                       "plan work upload");
+      if (s == SDN_OK)
+        s = hip_check(hipMemcpyAsync(tstart, hstart.data(), (size_t)nb * 4, hipMemcpyHostToDevice,
+                                     st),
+                      "plan offsets upload");
     }
-    // plan order: points sorted by tile, original order within a tile
+    // plan order: points sorted by tile and bank class (original order
+    // within a class), then interleaved over the classes of their tile
     if (s == SDN_OK)
       s = sort_pairs(reinterpret_cast<const unsigned *>(key), reinterpret_cast<unsigned *>(key2),
-                     ord_in, ord, m, key_bits((uint64_t)nb), st);
+                     ord_in, ord, m, key_bits((uint64_t)nb * kBankClasses), st);
     if (s == SDN_OK) {
-      hipLaunchKernelGGL(k_gather, grd, dim3(256), 0, st, ord, rec_tmp, frame_of_point, m, p->rec,
-                         p->pidx);
-      s = hip_check(hipGetLastError(), "plan gather kernel");
+      hipLaunchKernelGGL(k_place, grd, dim3(256), 0, st, reinterpret_cast<const unsigned *>(key2),
+                         ord, rec_tmp, frame_of_point, m, tstart, ccount, p->rec, p->pidx);
+      s = hip_check(hipGetLastError(), "plan placement kernel");
     }
     // per-point kernel weights
     if (s == SDN_OK) s = dalloc(&p->wts, (size_t)m * 3 * p->W, "plan weights");
@@ -570,7 +606,7 @@ sdn_status sdn_plan_create(sdn_plan *out, const int64_t shape[3], const float *t
     if (s == SDN_OK) s = hip_check(hipStreamSynchronize(st), "plan sync");
   }
   for (void *q : {(void *)key, (void *)key2, (void *)ord_in, (void *)ord, (void *)rec_tmp,
-                  (void *)count, (void *)bad, (void *)npv, (void *)ppos, (void *)vkey,
+                  (void *)count, (void *)ccount, (void *)tstart, (void *)bad, (void *)npv, (void *)ppos, (void *)vkey,
                   (void *)vkey2, (void *)vval})
     if (q) (void)hipFree(q);
   if (s != SDN_OK) {

@@ -60,6 +60,38 @@ def stage_bytes(g):
     }
 
 
+# flops of one gridding launch: every nonuniform point meets W^3 cells for
+# every (coil, channel) pair, one real weight times one complex value each
+# (2 FMAs = 4 flops)
+def stage_flops(g, W):
+    return {"interp": 4 * W ** 3 * g["M"] * g["P"], "spread": 4 * W ** 3 * g["M"] * g["P"]}
+
+
+# Kernel sources whose text the committed counter summary was taken from.
+_SOURCES = {"interp": "gridops.hip", "spread": "gridops.hip", "pre_fftx": "fft.hip",
+            "fft_y": "fft.hip", "fft_z": "fft.hip", "ifft_z": "fft.hip", "ifft_y": "fft.hip",
+            "post_ifftx": "fft.hip"}
+TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                            "hbm_traffic_c4.txt")
+
+
+def measured_traffic(stage):
+    """HBM bytes per launch of a stage from the committed FETCH_SIZE / WRITE_SIZE
+    summary, or None when there is none or the kernel source has changed since."""
+    import hashlib
+    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2408_02367_amd", "csrc",
+                       _SOURCES.get(stage, ""))
+    if not os.path.isfile(TRAFFIC_FILE) or not os.path.isfile(src):
+        return None
+    with open(src, "rb") as f:
+        digest = hashlib.sha256(f.read()).hexdigest()
+    for line in open(TRAFFIC_FILE):
+        parts = dict(kv.split("=", 1) for kv in line.split() if "=" in kv)
+        if parts.get("stage") == stage and parts.get("source_sha256") == digest:
+            return int(float(parts["hbm_bytes_per_launch"]))
+    return None
+
+
 def cpu_baseline(w, x, smaps, sample):
     """The FP64 oracle's gridding fwd+adj for one (coil, channel) pair of the
     workload: grid stages in full, point stages on a seeded random sample of
@@ -146,12 +178,17 @@ def main():
     torch.cuda.synchronize()
     plan.profile(True)
     plan.profile_read(reset=True)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(a.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(a.steps):
+    for e0, e1 in ev:
+        e0.record()
         step()
+        e1.record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    per_step = np.array([e0.elapsed_time(e1) for e0, e1 in ev])
     stages = plan.profile_read(reset=True)
     plan.profile(False)
     ms_step = (t1 - t0) * 1e3 / a.steps
@@ -193,6 +230,7 @@ def main():
     geo = dict(P=P, B=B, K=K, M=M, Nz=shape[0], Ny=shape[1], Nx=shape[2],
                nfz=info["fine"][0], nfy=info["fine"][1], nfx=info["fine"][2])
     sb = stage_bytes(geo)
+    sf = stage_flops(geo, info["W"])
     per_stage = {}
     for s, (ms, n) in stages.items():
         avg = ms / n
@@ -200,12 +238,24 @@ def main():
                         "avg_launch_ms": round(avg, 4)}
         if s in sb:
             per_stage[s]["algo_GBps"] = round(sb[s] / (avg * 1e-3) / 1e9, 1)
+        if s in sf:
+            per_stage[s]["TFLOPs"] = round(sf[s] / (avg * 1e-3) / 1e12, 2)
     dom = max((s for s in stages if s in sb), key=lambda s: stages[s][0])
     dom_avg_s = stages[dom][0] / stages[dom][1] * 1e-3
-    achieved = sb[dom] / dom_avg_s / 1e9
-    roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0,
-                "unit": "GB/s", "frac": round(achieved / 8000.0, 4), "traffic": None,
-                "algo_bytes_per_launch": sb[dom]}
+    if dom in sf:
+        # arithmetic intensity above the FP32 ridge (157.3 TFLOP/s / 8 TB/s)
+        achieved = sf[dom] / dom_avg_s / 1e12
+        roofline = {"kernel": dom, "bound": "alu", "achieved": round(achieved, 2), "peak": 157.3,
+                    "unit": "TFLOP/s", "frac": round(achieved / 157.3, 4),
+                    "algo_flops_per_launch": sf[dom], "algo_bytes_per_launch": sb[dom],
+                    "algo_hbm_GBps": round(sb[dom] / dom_avg_s / 1e9, 1)}
+    else:
+        achieved = sb[dom] / dom_avg_s / 1e9
+        roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0,
+                    "unit": "GB/s", "frac": round(achieved / 8000.0, 4),
+                    "algo_bytes_per_launch": sb[dom]}
+    roofline["traffic"] = measured_traffic(dom)
+    roofline["avg_launch_ms"] = round(dom_avg_s * 1e3, 4)
 
     out = {
         "metric": "NUFFT fwd+adj nonuniform pts*ch/s (minibatch DC gradient)",
@@ -215,6 +265,7 @@ def main():
         "steps": a.steps,
         "warmup": a.warmup,
         "ms_per_step": round(ms_step, 3),
+        "step_ms_p10_p50_p90": [round(float(np.percentile(per_step, q)), 3) for q in (10, 50, 90)],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

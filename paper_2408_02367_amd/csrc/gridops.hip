@@ -125,23 +125,31 @@ __global__ void __launch_bounds__(kIThreads) k_interp(InterpDev a) {
         (e0 < W ? wx[e0] : e0 < 2 * W ? wy[e0 - W] : wz[e0 - 2 * W]) = t.x;
         (e1 < W ? wx[e1] : e1 < 2 * W ? wy[e1 - W] : wz[e1 - 2 * W]) = t.y;
       }
+      // plane by plane: the W x W cells of a plane are read into registers
+      // first, so the reads of a plane are in flight together
       float ur = 0.f, ui = 0.f;
+      const float2 *base = tile + (lz * PY + ly) * PX + lx;
 #pragma unroll
       for (int az = 0; az < W; ++az) {
+        float2 v[W][W];
+#pragma unroll
+        for (int ay = 0; ay < W; ++ay)
+#pragma unroll
+          for (int i = 0; i < W; ++i) v[ay][i] = base[(az * PY + ay) * PX + i];
+        float pr = 0.f, pi = 0.f;
 #pragma unroll
         for (int ay = 0; ay < W; ++ay) {
-          const float2 *row = tile + ((lz + az) * PY + (ly + ay)) * PX + lx;
           float tr = 0.f, ti = 0.f;
 #pragma unroll
           for (int i = 0; i < W; ++i) {
-            const float2 v = row[i];
-            tr = fmaf(wx[i], v.x, tr);
-            ti = fmaf(wx[i], v.y, ti);
+            tr = fmaf(wx[i], v[ay][i].x, tr);
+            ti = fmaf(wx[i], v[ay][i].y, ti);
           }
-          const float wzy = wz[az] * wy[ay];
-          ur = fmaf(wzy, tr, ur);
-          ui = fmaf(wzy, ti, ui);
+          pr = fmaf(wy[ay], tr, pr);
+          pi = fmaf(wy[ay], ti, pi);
         }
+        ur = fmaf(wz[az], pr, ur);
+        ui = fmaf(wz[az], pi, ui);
       }
       const float2 u = make_float2(ur, ui);
       if constexpr (MIX) {

@@ -68,7 +68,15 @@ typedef struct {
                               0 = library choice (2048)                              */
   size_t workspace_budget; /* bytes of fine-grid workspace; 0 = unlimited.  Calls
                               whose coil minibatch does not fit run coil-chunked.   */
+  int spread_engine;       /* type-1 spreading kernel: SDN_SPREAD_AUTO (default),
+                              SDN_SPREAD_GATHER (vector ALU gather into registers) or
+                              SDN_SPREAD_MATRIX (matrix cores, split fp16 products
+                              with FP32 accumulation; needs every fine axis >= 16
+                              and >= 2 channels per call, else the gather runs)     */
 } sdn_opts;
+
+/* Values of sdn_opts.spread_engine. */
+enum { SDN_SPREAD_AUTO = 0, SDN_SPREAD_GATHER = 1, SDN_SPREAD_MATRIX = 2 };
 
 /* Plan facts, for callers and tests. */
 typedef struct {

@@ -48,7 +48,11 @@ class SdnError(RuntimeError):
 
 class Opts(ctypes.Structure):
     _fields_ = [("W", ctypes.c_int), ("sigma", ctypes.c_double), ("tile", ctypes.c_int),
-                ("max_points_per_item", ctypes.c_int), ("workspace_budget", ctypes.c_size_t)]
+                ("max_points_per_item", ctypes.c_int), ("workspace_budget", ctypes.c_size_t),
+                ("spread_engine", ctypes.c_int)]
+
+
+SPREAD_ENGINES = {"auto": 0, "gather": 1, "matrix": 2}
 
 
 class PlanInfo(ctypes.Structure):
@@ -148,7 +152,7 @@ class Plan:
     """
 
     def __init__(self, traj, shape, sigma=2.0, W=6, frame_of_point=None, T=None, tile=0,
-                 max_points_per_item=0, workspace_budget=0):
+                 max_points_per_item=0, workspace_budget=0, spread_engine="auto"):
         L = lib()
         self._h = ctypes.c_void_p()
         traj = torch.as_tensor(traj)
@@ -170,6 +174,7 @@ class Plan:
         L.sdn_default_opts(ctypes.byref(o))
         o.W, o.sigma, o.tile = int(W), float(sigma), int(tile)
         o.max_points_per_item, o.workspace_budget = int(max_points_per_item), int(workspace_budget)
+        o.spread_engine = SPREAD_ENGINES[spread_engine]
         sh = (ctypes.c_int64 * 3)(*self.shape)
         with torch.cuda.device(dev):
             _check(L.sdn_plan_create(ctypes.byref(self._h), sh,

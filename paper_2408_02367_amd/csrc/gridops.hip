@@ -377,6 +377,246 @@ __global__ void __launch_bounds__(64) k_spread(SpreadDev a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Spreading as a matrix product on the matrix cores.
+//
+// For one 8 x 8 x 8 block, the sum over its list entries p is
+//   H[(y,x), (k, re/im, z)] = sum_p A[(y,x), p] B[p, (k, re/im, z)],
+//   A = wy_p(y) wx_p(x),   B = wz_p(z) (v_{p,k}).re/im,
+// a product of a 64 x P and a P x 16K matrix, done 32 entries at a time with
+// v_mfma_f32_16x16x32_f16.  FP32 accuracy is kept by splitting each operand
+// into fp16 hi + lo parts (x = hi + lo to ~2^-22) and summing the three
+// products hi.hi + hi.lo + lo.hi in the FP32 accumulators; the values are
+// scaled by a power of two s (from the largest input magnitude) so that they
+// sit in fp16 range, and the block is scaled back by 1/s on write-out.
+// Used when every fine axis is at least 16 cells, so that no kernel support
+// can touch both ends of a block.
+typedef _Float16 sdn_half8 __attribute__((ext_vector_type(8)));
+typedef float sdn_float4v __attribute__((ext_vector_type(4)));
+
+constexpr int kMmaBatch = 32;                 // list entries per matrix step
+constexpr int kWinPad = 8;                    // zeros before a weight row
+constexpr int kWinLen = 24;                   // zeros, W weights, zeros
+
+// fp16 hi/lo split of two floats, packed as (entry p0, entry p1) pairs.
+__device__ __forceinline__ void split2(float a0, float a1, unsigned &hi, unsigned &lo) {
+  const auto h = __builtin_amdgcn_cvt_pkrtz(a0, a1);
+  const float r0 = a0 - (float)h[0], r1 = a1 - (float)h[1];
+  const auto l = __builtin_amdgcn_cvt_pkrtz(r0, r1);
+  hi = __builtin_bit_cast(unsigned, h);
+  lo = __builtin_bit_cast(unsigned, l);
+}
+
+// Offset of the block start against a point's first node along one axis,
+// as the index shift into the point's zero-padded weight row.
+__device__ __forceinline__ int win_shift(int o, int l0, int nf, int W) {
+  int s = o - l0;
+  s += s < -kWinPad ? nf : 0;
+  s -= s > W ? nf : 0;
+  return min(max(s, -kWinPad), W);
+}
+
+// Power-of-two scale that brings the largest value to below 2^14.
+__device__ __forceinline__ float value_scale(const unsigned *absmax, bool mix) {
+  const float m = __uint_as_float(absmax[0]) * (mix ? 2.f * __uint_as_float(absmax[1]) : 1.f);
+  if (!(m > 0.f) || !(m < 3.0e38f)) return 1.f;
+  int e;
+  (void)frexpf(m, &e);
+  return ldexpf(1.f, 14 - e);
+}
+
+// Point data of one list entry, fetched a batch ahead of its use: lanes
+// 0..31 take the x/y half (first node, x and y weights), lanes 32..63 the
+// z/value half (z weights, frame and the input value).
+template <int W>
+struct MmaFetch {
+  int l0;
+  float w[2 * W];
+  int frame;
+  float2 v;
+};
+
+template <int W, bool MIX, int K>
+__device__ __forceinline__ void mma_fetch(const SpreadDev &a, const int4 &it, int grp, int b0,
+                                          int p, int h, MmaFetch<W> &f) {
+  const bool ok = b0 + p < it.z;
+  const int raw = ok ? a.vlist[it.y + b0 + p] : 0;
+  // a complemented entry is a support that starts in an earlier block (z
+  // offset below 0); on grids of at least 16 cells per axis no support
+  // meets a block twice, so it is an ordinary entry here
+  const int j = raw < 0 ? ~raw : raw;
+  const float *w = a.wts + (size_t)j * 3 * W;
+  if (h == 0) {
+    f.l0 = __float_as_int(a.rec[j].w);
+#pragma unroll
+    for (int i = 0; i < 2 * W; ++i) f.w[i] = ok ? w[i] : 0.f;
+  } else {
+#pragma unroll
+    for (int i = 0; i < W; ++i) f.w[i] = ok ? w[2 * W + i] : 0.f;
+    const int2 id = a.pidx[j];
+    f.frame = id.x;
+    const int col = a.src_plan ? j : id.y;
+    f.v = ok ? a.src[(size_t)grp * (MIX ? 1 : K) * a.M + col] : make_float2(0.f, 0.f);
+  }
+}
+
+template <int W, bool MIX, int K>
+__global__ void __launch_bounds__(64) k_spread_mma(SpreadDev a, const unsigned *absmax) {
+  __shared__ float wrow[3][kMmaBatch][kWinLen];
+  __shared__ float vals[kMmaBatch][2 * K + 1];
+  __shared__ int shifts[kMmaBatch];
+  const int4 it = a.items[blockIdx.x];
+  const int grp = blockIdx.y;
+  const int lane = threadIdx.x;
+  const int bzi = it.x / (a.nbx * a.nby);
+  const int rem = it.x - bzi * (a.nbx * a.nby);
+  const int byi = rem / a.nbx, bxi = rem - byi * a.nbx;
+  const int ox = bxi * kSB, oy = byi * kSB, oz = bzi * kSB;
+  const float s = value_scale(absmax, MIX);
+
+  // zero the weight rows once; each batch rewrites only the W weights
+  for (int i = lane; i < 3 * kMmaBatch * kWinLen; i += 64) (&wrow[0][0][0])[i] = 0.f;
+
+  sdn_float4v acc[4][K];
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[t][k] = sdn_float4v{0.f, 0.f, 0.f, 0.f};
+
+  const int p = lane & (kMmaBatch - 1);   // fetch: this lane's entry
+  const int h = lane / kMmaBatch;         // 0: x/y half, 1: z/value half
+  const int r16 = lane & 15;              // fragment row (A) / column (B)
+  const int e0 = 8 * (lane >> 4);         // fragment entries e0 .. e0+7
+  const int fx = r16 & 7, fy = r16 >> 3;  // A: x and y offset of the row
+  const int fz = r16 & 7, fri = r16 >> 3; // B: z and re/im of the column
+
+  MmaFetch<W> f;
+  if (it.z > 0) mma_fetch<W, MIX, K>(a, it, grp, 0, p, h, f);
+  for (int b0 = 0; b0 < it.z; b0 += kMmaBatch) {
+    __syncthreads();
+    // stage this batch's point data
+    if (h == 0) {
+      const unsigned u = (unsigned)f.l0;
+      const int sx = win_shift(ox, (int)(u & 1023u), a.nfx, W);
+      const int sy = win_shift(oy, (int)((u >> 10) & 1023u), a.nfy, W);
+      const int sz = win_shift(oz, (int)((u >> 20) & 1023u), a.nfz, W);
+      shifts[p] = (sx + kWinPad) | ((sy + kWinPad) << 8) | ((sz + kWinPad) << 16);
+#pragma unroll
+      for (int i = 0; i < W; ++i) {
+        wrow[0][p][kWinPad + i] = f.w[i];
+        wrow[1][p][kWinPad + i] = f.w[W + i];
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < W; ++i) wrow[2][p][kWinPad + i] = f.w[i];
+      if constexpr (MIX) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const float2 v = cmulc(f.v, a.V[(size_t)f.frame * K + k]);
+          vals[p][2 * k] = v.x * s;
+          vals[p][2 * k + 1] = v.y * s;
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const bool ok = b0 + p < it.z;
+          const int raw = ok ? a.vlist[it.y + b0 + p] : 0;
+          const int j = raw < 0 ? ~raw : raw;
+          const int col = a.src_plan ? j : a.pidx[j].y;
+          const float2 v = ok ? a.src[(size_t)(grp * K + k) * a.M + col] : make_float2(0.f, 0.f);
+          vals[p][2 * k] = v.x * s;
+          vals[p][2 * k + 1] = v.y * s;
+        }
+      }
+    }
+    // the next batch's point data is in flight during this batch's products
+    if (b0 + kMmaBatch < it.z) mma_fetch<W, MIX, K>(a, it, grp, b0 + kMmaBatch, p, h, f);
+    __syncthreads();
+    // fragments straight into registers: A[(y,x)][e] = wy wx, B[e][(re/im,z)] = wz v
+    float ax[4][8], bz[8];
+    float bvv[K][8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int q = e0 + e;
+      const int sh = shifts[q];
+      const int sx = sh & 255, sy = (sh >> 8) & 255, sz = (sh >> 16) & 255;
+      const float wxv = wrow[0][q][sx + fx];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) ax[t][e] = wrow[1][q][sy + 2 * t + fy] * wxv;
+      bz[e] = wrow[2][q][sz + fz];
+#pragma unroll
+      for (int k = 0; k < K; ++k) bvv[k][e] = bz[e] * vals[q][2 * k + fri];
+    }
+    sdn_half8 ah[4], al[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      unsigned hi[4], lo[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) split2(ax[t][2 * e], ax[t][2 * e + 1], hi[e], lo[e]);
+      ah[t] = __builtin_bit_cast(sdn_half8, make_uint4(hi[0], hi[1], hi[2], hi[3]));
+      al[t] = __builtin_bit_cast(sdn_half8, make_uint4(lo[0], lo[1], lo[2], lo[3]));
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      unsigned hi[4], lo[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) split2(bvv[k][2 * e], bvv[k][2 * e + 1], hi[e], lo[e]);
+      const sdn_half8 bh = __builtin_bit_cast(sdn_half8, make_uint4(hi[0], hi[1], hi[2], hi[3]));
+      const sdn_half8 bl = __builtin_bit_cast(sdn_half8, make_uint4(lo[0], lo[1], lo[2], lo[3]));
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        acc[t][k] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[t], bh, acc[t][k], 0, 0, 0);
+        acc[t][k] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[t], bl, acc[t][k], 0, 0, 0);
+        acc[t][k] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[t], bh, acc[t][k], 0, 0, 0);
+      }
+    }
+  }
+  // lane holds rows (y,x) = 16t + 4(lane/16) + i, column (re/im, z) = lane % 16
+  const float inv = 1.f / s;
+  const int ri = (lane >> 3) & 1, z = lane & 7;
+  if (it.w >= 0) {
+    float *pp = reinterpret_cast<float *>(a.part + ((size_t)it.w * a.groups + grp) * K * kSBCells);
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int row = 16 * t + 4 * (lane >> 4) + i;
+          pp[((size_t)k * kSBCells + z * 64 + row) * 2 + ri] = acc[t][k][i] * inv;
+        }
+    return;
+  }
+  if (oz + z >= a.nfz) return;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    float *gp = reinterpret_cast<float *>(a.grid + (size_t)(grp * K + k) * a.G);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = 16 * t + 4 * (lane >> 4) + i;
+        const int gx = ox + (row & 7), gy = oy + (row >> 3);
+        if (gx < a.nfx && gy < a.nfy)
+          gp[(((size_t)(oz + z) * a.nfy + gy) * a.nfx + gx) * 2 + ri] = acc[t][k][i] * inv;
+      }
+  }
+}
+
+// Largest |component| of n floats, as float bits (non-negative floats order
+// like their bit patterns) into *out, which starts at zero.
+__global__ void __launch_bounds__(256) k_absmax(const float *x, size_t n, unsigned *out) {
+  float m = 0.f;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
+    m = fmaxf(m, fabsf(x[i]));
+  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+  if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(m));
+}
+
+__global__ void k_zero_u32(unsigned *p, int n) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
+}
+
 // grid = (split blocks, groups): sum the partial blocks of a crowded block.
 __global__ void __launch_bounds__(kThreads) k_spread_reduce(SpreadDev a, const int4 *splits, int K) {
   const int4 sp = splits[blockIdx.x];
@@ -528,6 +768,25 @@ size_t spread_part_elems(const sdn_plan_s &p, int groups, int K) {
 
 namespace {
 template <int W, bool MIX>
+hipError_t spread_mma(const SpreadDev &d, int K, dim3 grd, const unsigned *absmax, hipStream_t st) {
+  switch (K) {
+#define SDN_SPM(KV) \
+  case KV: hipLaunchKernelGGL((k_spread_mma<W, MIX, KV>), grd, dim3(64), 0, st, d, absmax); break;
+    SDN_SPM(2) SDN_SPM(3) SDN_SPM(4) SDN_SPM(5) SDN_SPM(6) SDN_SPM(7) SDN_SPM(8)
+#undef SDN_SPM
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// The matrix-core spreading needs every fine axis >= 16 cells (no support
+// touches both ends of a block) and at least two channels per group.
+bool use_spread_mma(const sdn_plan_s &p, int K) {
+  if (p.spread_engine == SDN_SPREAD_GATHER) return false;
+  return K >= 2 && p.ax[0].nf >= 16 && p.ax[1].nf >= 16 && p.ax[2].nf >= 16 && p.absmax != nullptr;
+}
+
+template <int W, bool MIX>
 hipError_t spread_k(const SpreadDev &d, int K, dim3 grd, hipStream_t st) {
   switch (K) {
 #define SDN_SPK(KV) \
@@ -563,10 +822,28 @@ hipError_t launch_spread(const sdn_plan_s &p, const SpreadArgs &a, hipStream_t s
   const bool mix = a.V != nullptr;
   dim3 grd((unsigned)p.nsitems, (unsigned)a.groups);
   hipError_t e;
-  switch (p.W) {
-    case 4: e = mix ? spread_k<4, true>(d, a.K, grd, st) : spread_k<4, false>(d, a.K, grd, st); break;
-    case 8: e = mix ? spread_k<8, true>(d, a.K, grd, st) : spread_k<8, false>(d, a.K, grd, st); break;
-    default: e = mix ? spread_k<6, true>(d, a.K, grd, st) : spread_k<6, false>(d, a.K, grd, st); break;
+  if (use_spread_mma(p, a.K)) {
+    // value scale: the largest input component (and of V when mixing)
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, p.absmax, 2);
+    const size_t nsrc = (size_t)a.groups * (mix ? 1 : a.K) * p.M * 2;
+    const unsigned nblk = (unsigned)std::min<size_t>(2048, (nsrc + 1023) / 1024);
+    hipLaunchKernelGGL(k_absmax, dim3(nblk), dim3(256), 0, st, (const float *)a.src, nsrc, p.absmax);
+    if (mix)
+      hipLaunchKernelGGL(k_absmax, dim3(1), dim3(256), 0, st, (const float *)a.V,
+                         (size_t)p.T * a.K * 2, p.absmax + 1);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    switch (p.W) {
+      case 4: e = mix ? spread_mma<4, true>(d, a.K, grd, p.absmax, st) : spread_mma<4, false>(d, a.K, grd, p.absmax, st); break;
+      case 8: e = mix ? spread_mma<8, true>(d, a.K, grd, p.absmax, st) : spread_mma<8, false>(d, a.K, grd, p.absmax, st); break;
+      default: e = mix ? spread_mma<6, true>(d, a.K, grd, p.absmax, st) : spread_mma<6, false>(d, a.K, grd, p.absmax, st); break;
+    }
+  } else {
+    switch (p.W) {
+      case 4: e = mix ? spread_k<4, true>(d, a.K, grd, st) : spread_k<4, false>(d, a.K, grd, st); break;
+      case 8: e = mix ? spread_k<8, true>(d, a.K, grd, st) : spread_k<8, false>(d, a.K, grd, st); break;
+      default: e = mix ? spread_k<6, true>(d, a.K, grd, st) : spread_k<6, false>(d, a.K, grd, st); break;
+    }
   }
   if (e != hipSuccess || p.nsplit == 0) return e;
   hipLaunchKernelGGL(k_spread_reduce, dim3((unsigned)p.nsplit, (unsigned)a.groups), dim3(kThreads),

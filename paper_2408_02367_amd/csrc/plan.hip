@@ -290,6 +290,8 @@ void free_plan_memory(sdn_plan_s *p) {
     p->dinv[d] = nullptr;
     p->tw[d] = nullptr;
   }
+  if (p->absmax) (void)hipFree(p->absmax);
+  p->absmax = nullptr;
   if (p->rec) (void)hipFree(p->rec);
   if (p->pidx) (void)hipFree(p->pidx);
   if (p->frame_user) (void)hipFree(p->frame_user);
@@ -335,6 +337,7 @@ void sdn_default_opts(sdn_opts *o) {
   o->tile = 0;
   o->max_points_per_item = 0;
   o->workspace_budget = 0;
+  o->spread_engine = SDN_SPREAD_AUTO;
 }
 
 const char *sdn_last_error(void) { return sdn::last_error(); }
@@ -377,6 +380,9 @@ sdn_status sdn_plan_create(sdn_plan *out, const int64_t shape[3], const float *t
   p->ncoef = kernel_ncoef(o.W);
   kernel_coefficients(o.W, beta, p->ncoef, &p->coef);
   p->budget = o.workspace_budget;
+  if (o.spread_engine < SDN_SPREAD_AUTO || o.spread_engine > SDN_SPREAD_MATRIX)
+    return delete p, fail(SDN_E_INVALID, "sdn_plan_create: unknown spread_engine");
+  p->spread_engine = o.spread_engine;
   p->max_points_per_item = o.max_points_per_item > 0 ? o.max_points_per_item : kItemCap;
   if (p->max_points_per_item > kItemCap)
     return delete p, fail(SDN_E_INVALID, "sdn_plan_create: max_points_per_item above 2048");
@@ -421,6 +427,7 @@ sdn_status sdn_plan_create(sdn_plan *out, const int64_t shape[3], const float *t
       s = hip_check(hipMemcpy(p->tw[d], tw.data(), tw.size() * 4, hipMemcpyHostToDevice),
                     "plan tables upload");
   }
+  if (s == SDN_OK) s = dalloc(&p->absmax, 4, "plan scale words");
   p->nbins = (int64_t)p->ax[0].ntile * p->ax[1].ntile * p->ax[2].ntile;
   p->nsbins = (int64_t)p->ax[0].nsblk * p->ax[1].nsblk * p->ax[2].nsblk;
 

@@ -111,6 +111,8 @@ struct sdn_plan_s {
   size_t kbuf_cap = 0;
   float2 *part = nullptr;    // partial tiles of split spreading items
   size_t part_cap = 0;
+  unsigned *absmax = nullptr; // 4 words: largest input magnitudes of a spreading call
+  int spread_engine = 0;      // SDN_SPREAD_*
 
   // per-stage event timing
   struct StageEvents {

@@ -75,7 +75,7 @@ constexpr int kIThreads = 512;                // interpolation workgroup
 
 // grid = (items, groups).  Mix mode: a group is one coil and its K channels,
 // output y_b = sum_k V[t][k] u_k (+ DC epilogue), the running sums kept in
-// LDS behind the staged tile.  Otherwise a group is K independent channels
+// registers by the thread that owns the point.  Otherwise a group is K independent channels
 // with outputs y_{gK+k} = u_k.  The plan orders the points of a tile so
 // that every 16 consecutive points start at tile cells of distinct residues
 // mod 16; each 16-lane group's 8-byte LDS reads then hit distinct banks at
@@ -93,11 +93,13 @@ __global__ void __launch_bounds__(kIThreads) k_interp(InterpDev a) {
   const int ox = tx * g.bx, oy = ty * g.by, oz = tz * g.bz;
   const int PX = g.bx + W - 1, PY = g.by + W - 1, PZ = g.bz + W - 1;
   const int ncell = PX * PY * PZ;
-  float2 *acc = tile + ncell;   // [kItemCap] running subspace sums (mix mode)
-
-  if constexpr (MIX) {
-    for (int q = tid; q < wi.z; q += kIThreads) acc[q] = make_float2(0.f, 0.f);
-  }
+  // running subspace sums of this thread's points (mix mode): point
+  // q = tid + i kIThreads keeps its sum in acc[i] across the channels
+  constexpr int kPts = kItemCap / kIThreads;
+  static_assert(kItemCap % kIThreads == 0, "an item is a whole number of thread passes");
+  float2 acc[kPts];
+#pragma unroll
+  for (int i = 0; i < kPts; ++i) acc[i] = make_float2(0.f, 0.f);
   for (int k = 0; k < a.K; ++k) {
     const float2 *gp = a.grid + (size_t)(grp * a.K + k) * g.G;
     for (int e = tid; e < ncell; e += kIThreads) {
@@ -110,7 +112,9 @@ __global__ void __launch_bounds__(kIThreads) k_interp(InterpDev a) {
     }
     __syncthreads();
 #pragma unroll 1
-    for (int q = tid; q < wi.z; q += kIThreads) {
+    for (int i = 0; i < kPts; ++i) {
+      const int q = tid + i * kIThreads;
+      if (q >= wi.z) break;
       const int2 id = a.pidx[wi.y + q];
       int lx, ly, lz;
       unpack_l0(a.rec[wi.y + q].w, lx, ly, lz);
@@ -119,41 +123,49 @@ __global__ void __launch_bounds__(kIThreads) k_interp(InterpDev a) {
       const float2 *wp = reinterpret_cast<const float2 *>(a.wts + (size_t)(wi.y + q) * 3 * W);
       float wx[W], wy[W], wz[W];
 #pragma unroll
-      for (int i = 0; i < 3 * W / 2; ++i) {
-        const float2 t = wp[i];
-        const int e0 = 2 * i, e1 = 2 * i + 1;
+      for (int c = 0; c < 3 * W / 2; ++c) {
+        const float2 t = wp[c];
+        const int e0 = 2 * c, e1 = 2 * c + 1;
         (e0 < W ? wx[e0] : e0 < 2 * W ? wy[e0 - W] : wz[e0 - 2 * W]) = t.x;
         (e1 < W ? wx[e1] : e1 < 2 * W ? wy[e1 - W] : wz[e1 - 2 * W]) = t.y;
       }
-      // plane by plane: the W x W cells of a plane are read into registers
-      // first, so the reads of a plane are in flight together
+      // half a kernel plane at a time: its cells are read into registers
+      // first, so those reads are in flight together
+      static_assert(W % 2 == 0, "planes are read in halves");
       float ur = 0.f, ui = 0.f;
       const float2 *base = tile + (lz * PY + ly) * PX + lx;
 #pragma unroll
       for (int az = 0; az < W; ++az) {
-        float2 v[W][W];
-#pragma unroll
-        for (int ay = 0; ay < W; ++ay)
-#pragma unroll
-          for (int i = 0; i < W; ++i) v[ay][i] = base[(az * PY + ay) * PX + i];
         float pr = 0.f, pi = 0.f;
 #pragma unroll
-        for (int ay = 0; ay < W; ++ay) {
-          float tr = 0.f, ti = 0.f;
+        for (int hh = 0; hh < 2; ++hh) {
+          float2 v[W / 2][W];
 #pragma unroll
-          for (int i = 0; i < W; ++i) {
-            tr = fmaf(wx[i], v[ay][i].x, tr);
-            ti = fmaf(wx[i], v[ay][i].y, ti);
+          for (int ay = 0; ay < W / 2; ++ay)
+#pragma unroll
+            for (int c = 0; c < W; ++c) v[ay][c] = base[(az * PY + hh * (W / 2) + ay) * PX + c];
+#pragma unroll
+          for (int ay = 0; ay < W / 2; ++ay) {
+            float tr = 0.f, ti = 0.f;
+#pragma unroll
+            for (int c = 0; c < W; ++c) {
+              tr = fmaf(wx[c], v[ay][c].x, tr);
+              ti = fmaf(wx[c], v[ay][c].y, ti);
+            }
+            pr = fmaf(wy[hh * (W / 2) + ay], tr, pr);
+            pi = fmaf(wy[hh * (W / 2) + ay], ti, pi);
           }
-          pr = fmaf(wy[ay], tr, pr);
-          pi = fmaf(wy[ay], ti, pi);
         }
         ur = fmaf(wz[az], pr, ur);
         ui = fmaf(wz[az], pi, ui);
       }
       const float2 u = make_float2(ur, ui);
       if constexpr (MIX) {
-        acc[q] = cadd(acc[q], cmul(a.V[(size_t)id.x * a.K + k], u));
+        // register-resident sums: a select per slot instead of an indexed write
+        const float2 m = cmul(a.V[(size_t)id.x * a.K + k], u);
+#pragma unroll
+        for (int c = 0; c < kPts; ++c)
+          if (c == i) acc[c] = cadd(acc[c], m);
       } else {
         a.y[(size_t)(grp * a.K + k) * a.M + id.y] = u;
       }
@@ -162,16 +174,19 @@ __global__ void __launch_bounds__(kIThreads) k_interp(InterpDev a) {
   }
   if constexpr (MIX) {
     double my_loss = 0.0;
-    for (int q = tid; q < wi.z; q += kIThreads) {
+#pragma unroll
+    for (int i = 0; i < kPts; ++i) {
+      const int q = tid + i * kIThreads;
+      if (q >= wi.z) break;
       const int orig = a.pidx[wi.y + q].y;
       if constexpr (DC) {
         const float2 dv = a.d[(size_t)grp * a.M + orig];
-        const float2 df = csub(acc[q], dv);
+        const float2 df = csub(acc[i], dv);
         const float wt = a.w ? a.w[orig] : 1.f;
         my_loss += (double)wt * ((double)df.x * df.x + (double)df.y * df.y);
         a.r_plan[(size_t)grp * a.M + wi.y + q] = make_float2(2.f * wt * df.x, 2.f * wt * df.y);
       } else {
-        a.y[(size_t)grp * a.M + orig] = acc[q];
+        a.y[(size_t)grp * a.M + orig] = acc[i];
       }
     }
     if constexpr (DC) {
@@ -675,8 +690,8 @@ __global__ void k_mix_adj(const float2 *r, const float2 *V, const int32_t *frame
 
 // LDS of an interpolation workgroup: the staged tile plus the running sums.
 size_t interp_lds_bytes(const sdn_plan_s &p) {
-  return ((size_t)(p.ax[0].tile + p.W - 1) * (p.ax[1].tile + p.W - 1) * (p.ax[2].tile + p.W - 1) +
-          kItemCap) * sizeof(float2);
+  return (size_t)(p.ax[0].tile + p.W - 1) * (p.ax[1].tile + p.W - 1) * (p.ax[2].tile + p.W - 1) *
+         sizeof(float2);
 }
 
 namespace {

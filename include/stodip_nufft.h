@@ -184,7 +184,10 @@ SDN_API sdn_status sdn_mrf_adjoint_plain(sdn_plan plan, const void *y, int K, co
                                  int C, const int32_t *coil_idx, int B, const void *V,
                                  void *x_out, int accumulate, void *stream);
 
-/* Device workspace (bytes) a call with B coils and K channels would hold. */
+/* Device workspace (bytes) a call with B coils and K channels would hold:
+ * the fine grids of one pass (all B coils, or the coil chunk the budget
+ * allows), the k-space residual of those coils and the partial blocks of
+ * split spreading items. */
 SDN_API sdn_status sdn_workspace_size(sdn_plan plan, int B, int K, size_t *bytes);
 
 /* Release the plan's cached workspace (it is re-allocated on demand). */

@@ -409,7 +409,8 @@ sdn_status sdn_workspace_size(sdn_plan p, int B, int K, size_t *bytes) {
   if (!bytes || B < 1 || K < 1) return fail(SDN_E_INVALID, "sdn_workspace_size: bad argument");
   int per;
   SDN_TRY(channels_per_pass(*p, K, B, &per, "sdn_workspace_size"));
-  *bytes = ((size_t)per * K * fine_cells(*p) + (size_t)per * p->M) * sizeof(float2);
+  *bytes = ((size_t)per * K * fine_cells(*p) + (size_t)per * p->M +
+            spread_part_elems(*p, per, K)) * sizeof(float2);
   return SDN_OK;
 }
 

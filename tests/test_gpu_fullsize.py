@@ -16,7 +16,8 @@ import torch
 
 import paper_2408_02367_amd as sdn
 import workloads as wl
-from gpu_common import TOL, c64, cimg, host, rel, to_gpu, uniform_points
+from gpu_common import (TOL, c64, cimg, direct_adjoint_at, direct_forward_at, host, rel, to_gpu,
+                        uniform_points)
 from oracle import gridding, nudft
 from oracle import mrf as omrf
 
@@ -76,52 +77,13 @@ def big():
                 ci_local=np.arange(len(ci), dtype=np.int32), V=c64(w["V"]))
 
 
-def _direct_forward_at(w, idx):
-    """y_b(j) for the sampled points j, from the definitions (direct NUDFT)."""
-    x, S, V = w["x"], w["smaps"], w["V"]
-    k = w["traj"][idx]
-    t = w["frame"][idx]
-    y = np.zeros((len(w["coil_idx"]), len(idx)), dtype=np.complex128)
-    for b, c in enumerate(w["coil_idx"]):
-        for kk in range(x.shape[0]):
-            y[b] += V[t, kk] * nudft.type2(S[c].astype(np.complex128) * x[kk], k, chunk=len(idx))
-    return y
-
-
-def _direct_adjoint_at(w, r, sel, chunk=200000):
-    """xbar_k at a Cartesian product of voxels, from the definitions."""
-    k = w["traj"].astype(np.float64)
-    V = w["V"].astype(np.complex128)
-    t = w["frame"]
-    shape = w["shape"]
-    mz, my, mx = (nudft.modes(n)[np.asarray(s)] for n, s in zip(shape, sel))
-    K = V.shape[1]
-    B = r.shape[0]
-    acc = np.zeros((B, K, len(mz), len(my), len(mx)), dtype=np.complex128)
-    for a in range(0, k.shape[0], chunk):
-        b_ = min(k.shape[0], a + chunk)
-        ex = np.exp(1j * np.outer(k[a:b_, 0], mx))
-        ey = np.exp(1j * np.outer(k[a:b_, 1], my))
-        ez = np.exp(1j * np.outer(k[a:b_, 2], mz))
-        E = (ez[:, :, None, None] * ey[:, None, :, None] * ex[:, None, None, :]).reshape(b_ - a, -1)
-        cv = np.conj(V[t[a:b_]])                                   # [m, K]
-        for b in range(B):
-            coef = cv * r[b, a:b_, None]                            # [m, K]
-            acc[b] += (coef.T @ E).reshape(K, len(mz), len(my), len(mx))
-    out = np.zeros((K, len(mz), len(my), len(mx)), dtype=np.complex128)
-    for b, c in enumerate(w["coil_idx"]):
-        sc = np.conj(w["smaps"][c][np.ix_(*sel)].astype(np.complex128))
-        out += sc[None] * acc[b]
-    return out
-
-
 def test_benchmark_size_forward_sampled_points(big):
     w, p = big["w"], big["plan"]
     y = host(sdn.mrf_forward(p, big["x"], big["s"], big["ci_local"], big["V"]))
     idx = np.sort(np.random.default_rng(11).choice(w["traj"].shape[0], 96, replace=False))
     # the k-space centre is the hottest tile: sample it too
     idx = np.unique(np.concatenate([idx, np.arange(0, 9600000, 1200)[:32]]))
-    ref = _direct_forward_at(w, idx)
+    ref = direct_forward_at(w, idx)
     assert rel(y[:, idx], ref) < TOL
 
 
@@ -131,7 +93,7 @@ def test_benchmark_size_adjoint_sampled_voxels(big):
     r = wl.random_kspace((B, M), 12)
     xb = host(sdn.mrf_adjoint(p, c64(r), big["s"], big["ci_local"], big["V"]))
     sel = ([20, 80, 131], [3, 79, 150], [0, 64, 80, 159])
-    ref = _direct_adjoint_at(w, r, sel)
+    ref = direct_adjoint_at(w, r, sel)
     assert rel(xb[(slice(None),) + np.ix_(*sel)], ref) < TOL
 
 

@@ -115,12 +115,13 @@ def phantom(shape, K, seed, blur=1.0):
     return out
 
 
-def coil_maps(shape, C, seed, radius=0.6, width=0.35, max_cycles=1.0):
+def coil_maps(shape, C, seed, radius=0.6, width=0.35, max_cycles=1.0, select=None):
     """C smooth coil maps S[C, Nz, Ny, Nx] (complex64) with sqrt(sum |S_c|^2) = 1.
 
     Gaussian-bump magnitudes centred on a Fibonacci sphere of ``radius``
     (FOV units) and a random linear phase of at most ``max_cycles`` cycles
-    per FOV.  Both factors are separable over the axes.
+    per FOV.  Both factors are separable over the axes.  ``select`` (indices)
+    returns only those maps, normalised by the root-sum-of-squares of all C.
     """
     g = rng(seed, COILS)
     nz, ny, nx = shape
@@ -133,13 +134,15 @@ def coil_maps(shape, C, seed, radius=0.6, width=0.35, max_cycles=1.0):
     gdir = g.standard_normal((C, 3))
     gdir /= np.linalg.norm(gdir, axis=1, keepdims=True)
     gvec = gdir * g.uniform(0.0, max_cycles, (C, 1))
-    maps = np.empty((C,) + tuple(shape), dtype=np.complex64)
+    keep = list(range(C)) if select is None else [int(c) for c in select]
+    maps = np.empty((len(keep),) + tuple(shape), dtype=np.complex64)
     rss = np.zeros(shape, dtype=np.float64)
     for c in range(C):
         f = [np.exp(-(ax[d] - ctr[c, d]) ** 2 / (2 * width ** 2))
              * np.exp(2j * np.pi * gvec[c, d] * ax[d]) for d in range(3)]
         m = f[2][:, None, None] * f[1][None, :, None] * f[0][None, None, :]
-        maps[c] = m
+        if c in keep:
+            maps[keep.index(c)] = m
         rss += np.abs(m) ** 2
     maps /= np.sqrt(rss).astype(np.float32)[None]
     return maps
@@ -197,8 +200,13 @@ CONFIGS = {
 SEEDS = {"c1": 1, "c2": 2, "c3": 3, "c3r128": 31, "c3r192": 32, "c4": 4, "c5": 5}
 
 
-def make(name, with_images=True):
-    """Draw the inputs of workload ``name`` as numpy arrays."""
+def make(name, with_images=True, minibatch_maps=False):
+    """Draw the inputs of workload ``name`` as numpy arrays.
+
+    ``minibatch_maps``: keep only the coil maps of the minibatch (in
+    minibatch order, still normalised over all C coils); ``coil_idx`` is
+    then 0 .. B-1 and ``coil_idx_global`` the coils they stand for.
+    """
     cfg = dict(CONFIGS[name])
     seed = SEEDS[name]
     traj, frame = spiral_trajectory(cfg["T"], cfg["L"], cfg["S"])
@@ -210,7 +218,14 @@ def make(name, with_images=True):
             out["V"] = None
         else:
             out["x"] = phantom(cfg["shape"], cfg["K"], seed)
-            out["smaps"] = coil_maps(cfg["shape"], cfg["C"], seed)
             out["V"] = subspace_basis(cfg["T"], cfg["K"], seed)
-        out["coil_idx"] = coil_minibatch(cfg["C"], cfg["B"], seed)
+        ci = coil_minibatch(cfg["C"], cfg["B"], seed)
+        out["coil_idx"] = ci
+        if name != "c1":
+            if minibatch_maps:
+                out["smaps"] = coil_maps(cfg["shape"], cfg["C"], seed, select=ci)
+                out["coil_idx_global"] = ci
+                out["coil_idx"] = np.arange(len(ci), dtype=np.int32)
+            else:
+                out["smaps"] = coil_maps(cfg["shape"], cfg["C"], seed)
     return out

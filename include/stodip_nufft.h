@@ -173,6 +173,43 @@ SDN_API sdn_status sdn_mrf_dc_grad(sdn_plan plan, const void *x, int K, const vo
                            const float *w, double *loss, void *grad, void *stream);
 
 /*
+ * Ragged volumes: a group of plans of different image shapes, each with its
+ * own trajectory (and V), evaluated as one call on one stream (the batched
+ * form over several volumes; Sec. 3 reconstructs many scans with one
+ * operator).  Every stage is launched per volume, in volume order; results
+ * equal those of the member plans called one by one.
+ *
+ *   sdn_group_create  plans: host array of n >= 1 live plans (not owned: they
+ *                     must outlive the group); the group holds n doubles of
+ *                     device memory for per-volume losses.
+ *   Per-volume arguments are host arrays of length n (x[v], smaps[v], C[v],
+ *   coil_idx[v], V[v], y[v], d[v], w[v] (entries may be NULL), grad[v]),
+ *   each entry laid out as for the single-plan call on plans[v]; K and B are
+ *   common to all volumes.
+ *   sdn_group_mrf_dc_grad: loss = dev double [1], the sum of the volumes'
+ *   losses (overwritten).
+ * Errors: as the single-plan calls; a failing volume stops the call.
+ */
+typedef struct sdn_group_s *sdn_group;
+SDN_API sdn_status sdn_group_create(sdn_group *out, const sdn_plan *plans, int n);
+SDN_API sdn_status sdn_group_destroy(sdn_group group);
+SDN_API sdn_status sdn_group_mrf_forward(sdn_group group, const void *const *x, int K,
+                                         const void *const *smaps, const int *C,
+                                         const int32_t *const *coil_idx, int B,
+                                         const void *const *V, void *const *y, void *stream);
+SDN_API sdn_status sdn_group_mrf_adjoint(sdn_group group, const void *const *y, int K,
+                                         const void *const *smaps, const int *C,
+                                         const int32_t *const *coil_idx, int B,
+                                         const void *const *V, void *const *x_out,
+                                         int accumulate, void *stream);
+SDN_API sdn_status sdn_group_mrf_dc_grad(sdn_group group, const void *const *x, int K,
+                                         const void *const *smaps, const int *C,
+                                         const int32_t *const *coil_idx, int B,
+                                         const void *const *V, const void *const *d,
+                                         const float *const *w, double *loss,
+                                         void *const *grad, void *stream);
+
+/*
  * The same operators evaluated the plain way, one (coil, channel) pair per
  * NUFFT with separate subspace-mix kernels: the per-coil/per-channel
  * baseline the batched calls are measured against.  Arguments as above.

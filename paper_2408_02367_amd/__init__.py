@@ -33,7 +33,8 @@ API = ["sdn_default_opts", "sdn_plan_create", "sdn_plan_destroy", "sdn_plan_get_
        "sdn_forward", "sdn_adjoint", "sdn_mrf_forward", "sdn_mrf_adjoint", "sdn_mrf_dc_grad",
        "sdn_mrf_forward_plain", "sdn_mrf_adjoint_plain", "sdn_workspace_size",
        "sdn_release_workspace", "sdn_profile_enable", "sdn_profile_read",
-       "sdn_kernel_tables", "sdn_last_error"]
+       "sdn_kernel_tables", "sdn_last_error", "sdn_group_create", "sdn_group_destroy",
+       "sdn_group_mrf_forward", "sdn_group_mrf_adjoint", "sdn_group_mrf_dc_grad"]
 
 # stage names, in the order of the sdn_stage enum
 STAGES = ["pre_fftx", "fft_y", "fft_z", "interp", "clear", "spread", "ifft_z", "ifft_y",
@@ -98,6 +99,13 @@ def lib():
                                         ctypes.POINTER(i32), ctypes.POINTER(i32),
                                         ctypes.POINTER(ctypes.c_float),
                                         ctypes.POINTER(ctypes.c_float)]
+        arr = ctypes.POINTER(vp)
+        gm = [vp, arr, i32, arr, ctypes.POINTER(i32), arr, i32, arr]
+        L.sdn_group_create.argtypes = [ctypes.POINTER(vp), arr, i32]
+        L.sdn_group_destroy.argtypes = [vp]
+        L.sdn_group_mrf_forward.argtypes = gm + [arr, vp]
+        L.sdn_group_mrf_adjoint.argtypes = gm + [arr, i32, vp]
+        L.sdn_group_mrf_dc_grad.argtypes = gm + [arr, arr, vp, arr, vp]
         L.sdn_last_error.argtypes = []
         L.sdn_last_error.restype = ctypes.c_char_p
         for name in API:
@@ -305,6 +313,83 @@ def mrf_dc_grad(plan, x, smaps, coil_idx, V, d, w=None, grad=None, loss=None):
                                  _dev(loss, torch.float64, "loss"),
                                  _dev(grad, torch.complex64, "grad"), _stream(x)))
     return loss, grad
+
+
+class PlanGroup:
+    """Ragged volumes: several plans (own shapes, trajectories and V)
+    evaluated by one call; per-volume arguments are lists in plan order."""
+
+    def __init__(self, plans):
+        self.plans = list(plans)
+        self._h = ctypes.c_void_p()
+        hs = (ctypes.c_void_p * len(self.plans))(*[p.handle.value for p in self.plans])
+        _check(lib().sdn_group_create(ctypes.byref(self._h), hs, len(self.plans)))
+
+    def close(self):
+        if self._h:
+            _check(lib().sdn_group_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _common(self, K, smaps, coil_idx, V):
+        n = len(self.plans)
+        if not (len(smaps) == len(coil_idx) == len(V) == n):
+            raise ValueError("one smaps, coil_idx and V per volume")
+        cis = [_mrf_common(p, K, s, c, v)[0] for p, s, c, v in zip(self.plans, smaps, coil_idx, V)]
+        B = len(cis[0])
+        if any(len(c) != B for c in cis):
+            raise ValueError("every volume takes the same number of coils")
+        keep = cis
+        cptrs = (ctypes.c_void_p * n)(*[c.ctypes.data for c in cis])
+        Cs = (ctypes.c_int * n)(*[s.shape[0] for s in smaps])
+        sp = (ctypes.c_void_p * n)(*[_dev(s, torch.complex64, "smaps").value for s in smaps])
+        vp = (ctypes.c_void_p * n)(*[_dev(v, torch.complex64, "V").value for v in V])
+        return B, keep, cptrs, Cs, sp, vp
+
+    def _ptrs(self, ts, name):
+        if len(ts) != len(self.plans):
+            raise ValueError(f"{name}: one tensor per volume ({len(self.plans)})")
+        return (ctypes.c_void_p * len(ts))(*[_dev(t, torch.complex64, name).value for t in ts])
+
+    def mrf_forward(self, x, smaps, coil_idx, V):
+        if len(x) != len(self.plans):
+            raise ValueError(f"x: one tensor per volume ({len(self.plans)})")
+        K = x[0].shape[0]
+        B, keep, cptrs, Cs, sp, vp = self._common(K, smaps, coil_idx, V)
+        ys = [torch.empty(B, p.M, dtype=torch.complex64, device=x[0].device) for p in self.plans]
+        _check(lib().sdn_group_mrf_forward(self._h, self._ptrs(x, "x"), K, sp, Cs, cptrs, B, vp,
+                                           self._ptrs(ys, "y"), _stream(x[0])))
+        return ys
+
+    def mrf_adjoint(self, y, smaps, coil_idx, V):
+        if len(y) != len(self.plans):
+            raise ValueError(f"y: one tensor per volume ({len(self.plans)})")
+        K = V[0].shape[1]
+        B, keep, cptrs, Cs, sp, vp = self._common(K, smaps, coil_idx, V)
+        xs = [torch.empty((K,) + p.shape, dtype=torch.complex64, device=y[0].device)
+              for p in self.plans]
+        _check(lib().sdn_group_mrf_adjoint(self._h, self._ptrs(y, "y"), K, sp, Cs, cptrs, B, vp,
+                                           self._ptrs(xs, "x_out"), 0, _stream(y[0])))
+        return xs
+
+    def mrf_dc_grad(self, x, smaps, coil_idx, V, d):
+        """(loss summed over volumes, per-volume gradients)."""
+        if len(x) != len(self.plans):
+            raise ValueError(f"x: one tensor per volume ({len(self.plans)})")
+        K = x[0].shape[0]
+        B, keep, cptrs, Cs, sp, vp = self._common(K, smaps, coil_idx, V)
+        grads = [torch.empty_like(t) for t in x]
+        loss = torch.empty(1, dtype=torch.float64, device=x[0].device)
+        _check(lib().sdn_group_mrf_dc_grad(self._h, self._ptrs(x, "x"), K, sp, Cs, cptrs, B, vp,
+                                           self._ptrs(d, "d"), None,
+                                           _dev(loss, torch.float64, "loss"),
+                                           self._ptrs(grads, "grad"), _stream(x[0])))
+        return loss, grads
 
 
 class MRFForward(torch.autograd.Function):

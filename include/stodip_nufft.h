@@ -221,6 +221,22 @@ SDN_API sdn_status sdn_mrf_adjoint_plain(sdn_plan plan, const void *y, int K, co
                                  int C, const int32_t *coil_idx, int B, const void *V,
                                  void *x_out, int accumulate, void *stream);
 
+/*
+ * Autotuner: builds candidate plans for one trajectory (interpolation tile
+ * edge 16x16x8 / 8 / 16, up to 2048 or 1024 points per work item, gather or
+ * matrix-core spreading, all other options from `base`), times three
+ * synthetic DC-gradient steps (coil minibatch B, K channels) of each on
+ * `stream`, and returns the fastest option set in *best and its time per
+ * step (ms) in *best_ms (may be NULL).  Arguments as sdn_plan_create; the
+ * tuner allocates its own synthetic inputs and frees everything before
+ * returning.  Candidates the device cannot run are skipped; SDN_E_UNSUPPORTED
+ * if none ran.  Synchronises `stream`.
+ */
+SDN_API sdn_status sdn_autotune(const int64_t shape[3], const float *traj, int64_t M,
+                                const int32_t *frame_of_point, int32_t T, int B, int K,
+                                const sdn_opts *base, sdn_opts *best, double *best_ms,
+                                void *stream);
+
 /* Device workspace (bytes) a call with B coils and K channels would hold:
  * the fine grids of one pass (all B coils, or the coil chunk the budget
  * allows), the k-space residual of those coils and the partial blocks of

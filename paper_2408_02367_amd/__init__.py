@@ -34,7 +34,8 @@ API = ["sdn_default_opts", "sdn_plan_create", "sdn_plan_destroy", "sdn_plan_get_
        "sdn_mrf_forward_plain", "sdn_mrf_adjoint_plain", "sdn_workspace_size",
        "sdn_release_workspace", "sdn_profile_enable", "sdn_profile_read",
        "sdn_kernel_tables", "sdn_last_error", "sdn_group_create", "sdn_group_destroy",
-       "sdn_group_mrf_forward", "sdn_group_mrf_adjoint", "sdn_group_mrf_dc_grad"]
+       "sdn_group_mrf_forward", "sdn_group_mrf_adjoint", "sdn_group_mrf_dc_grad",
+       "sdn_autotune"]
 
 # stage names, in the order of the sdn_stage enum
 STAGES = ["pre_fftx", "fft_y", "fft_z", "interp", "clear", "spread", "ifft_z", "ifft_y",
@@ -106,6 +107,9 @@ def lib():
         L.sdn_group_mrf_forward.argtypes = gm + [arr, vp]
         L.sdn_group_mrf_adjoint.argtypes = gm + [arr, i32, vp]
         L.sdn_group_mrf_dc_grad.argtypes = gm + [arr, arr, vp, arr, vp]
+        L.sdn_autotune.argtypes = [ctypes.POINTER(i64), vp, i64, vp, ctypes.c_int32, i32, i32,
+                                   ctypes.POINTER(Opts), ctypes.POINTER(Opts),
+                                   ctypes.POINTER(ctypes.c_double), vp]
         L.sdn_last_error.argtypes = []
         L.sdn_last_error.restype = ctypes.c_char_p
         for name in API:
@@ -313,6 +317,73 @@ def mrf_dc_grad(plan, x, smaps, coil_idx, V, d, w=None, grad=None, loss=None):
                                  _dev(loss, torch.float64, "loss"),
                                  _dev(grad, torch.complex64, "grad"), _stream(x)))
     return loss, grad
+
+
+TUNED_KEYS = ("tile", "max_points_per_item", "spread_engine")
+
+
+def tune_key(traj, shape, B, K, W=6, sigma=2.0, frame_of_point=None, device_name=""):
+    """Cache key of an autotuning result: image shape, minibatch, kernel and
+    a hash of the trajectory (and frames) as the library sees them."""
+    import hashlib
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(torch.as_tensor(traj).detach().cpu().numpy(),
+                                  dtype=np.float32).tobytes())
+    if frame_of_point is not None:
+        h.update(np.ascontiguousarray(torch.as_tensor(frame_of_point).detach().cpu().numpy(),
+                                      dtype=np.int32).tobytes())
+    return (f"{device_name}|shape={tuple(int(s) for s in shape)}|B={int(B)}|K={int(K)}|W={int(W)}"
+            f"|sigma={float(sigma)}|traj={h.hexdigest()[:32]}")
+
+
+def autotune(traj, shape, B, K, frame_of_point=None, T=None, W=6, sigma=2.0, cache=None,
+             workspace_budget=0):
+    """Plan options that make a DC step fastest for this trajectory.
+
+    Returns a dict of Plan keyword arguments (tile, max_points_per_item,
+    spread_engine) plus ``ms`` (time per synthetic step).  With ``cache``
+    (a JSON file path) a result for the same key is reused and new results
+    are stored.
+    """
+    import json
+    traj = torch.as_tensor(traj)
+    dev = traj.device if traj.is_cuda else torch.device("cuda", torch.cuda.current_device())
+    key = tune_key(traj, shape, B, K, W, sigma, frame_of_point,
+                   torch.cuda.get_device_name(dev))
+    table = {}
+    if cache is not None and os.path.exists(cache):
+        with open(cache) as f:
+            table = json.load(f)
+        if key in table:
+            return dict(table[key])
+    traj = traj.to(dev, torch.float32).contiguous()
+    M = int(traj.shape[0])
+    fptr = None
+    if frame_of_point is not None:
+        frame_of_point = torch.as_tensor(frame_of_point).to(dev, torch.int32).contiguous()
+        if T is None:
+            T = int(frame_of_point.max().item()) + 1 if M else 1
+        fptr = ctypes.c_void_p(frame_of_point.data_ptr())
+    base, best = Opts(), Opts()
+    lib().sdn_default_opts(ctypes.byref(base))
+    base.W, base.sigma, base.workspace_budget = int(W), float(sigma), int(workspace_budget)
+    ms = ctypes.c_double()
+    sh = (ctypes.c_int64 * 3)(*[int(s) for s in shape])
+    with torch.cuda.device(dev):
+        _check(lib().sdn_autotune(sh, ctypes.c_void_p(traj.data_ptr()) if M else None, M, fptr,
+                                  int(T) if T is not None else 1, int(B), int(K),
+                                  ctypes.byref(base), ctypes.byref(best), ctypes.byref(ms),
+                                  _stream(traj)))
+    engines = {v: k for k, v in SPREAD_ENGINES.items()}
+    out = {"tile": best.tile, "max_points_per_item": best.max_points_per_item,
+           "spread_engine": engines[best.spread_engine], "ms": ms.value}
+    if cache is not None:
+        table[key] = out
+        tmp = cache + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(table, f, indent=1, sort_keys=True)
+        os.replace(tmp, cache)
+    return out
 
 
 class PlanGroup:

@@ -20,10 +20,12 @@ What it computes (Sec. 2, Eq. 1-3 of the paper):
                  temporal-subspace mix), its adjoint, the data-consistency
                  loss of Eq. 2-3 and its gradient 2 A^H w (A x - d), plus a
                  frame-expansion brute force for tiny sizes.
+* ``dcf``      - the density compensation weights of Eq. 2 by Pipe-Menon
+                 fixed-point iteration with the gridding kernel.
 
 Every function is pinned by the ``-m "not gpu"`` tests in ``tests/`` to
 something other than itself (library FFTs on on-grid points, closed forms,
 Parseval, adjoint identities, quadrature, brute-force loops).
 """
 
-from . import nudft, kernel, gridding, mrf  # noqa: F401
+from . import nudft, kernel, gridding, mrf, dcf  # noqa: F401

@@ -222,6 +222,19 @@ SDN_API sdn_status sdn_mrf_adjoint_plain(sdn_plan plan, const void *y, int K, co
                                  void *x_out, int accumulate, void *stream);
 
 /*
+ * Density compensation weights for Eq. 2 (the paper uses a DCF as the
+ * loss's preconditioner, Sec. 2; it does not say how it is computed): the
+ * Pipe-Menon fixed-point iteration with the plan's gridding kernel
+ * (normalised to 1 at its centre on every axis), w_0 = 1,
+ *   w_{n+1} = w_n / (C w_n),  (C w)_j = sum_l phi(s_j - l) sum_i phi(s_i - l) w_i,
+ * evaluated as spreading onto the fine grid and interpolating back (no
+ * FFT).  w_out: dev float32 [M], user point order (overwritten); 1 <=
+ * iterations <= 1000.  Uses the plan's workspace (one fine grid and 2 M
+ * complex values).  The weights are the `w` argument of sdn_mrf_dc_grad.
+ */
+SDN_API sdn_status sdn_dcf_estimate(sdn_plan plan, int iterations, float *w_out, void *stream);
+
+/*
  * Autotuner: builds candidate plans for one trajectory (interpolation tile
  * edge 16x16x8 / 8 / 16, up to 2048 or 1024 points per work item, gather or
  * matrix-core spreading, all other options from `base`), times three

@@ -35,7 +35,7 @@ API = ["sdn_default_opts", "sdn_plan_create", "sdn_plan_destroy", "sdn_plan_get_
        "sdn_release_workspace", "sdn_profile_enable", "sdn_profile_read",
        "sdn_kernel_tables", "sdn_last_error", "sdn_group_create", "sdn_group_destroy",
        "sdn_group_mrf_forward", "sdn_group_mrf_adjoint", "sdn_group_mrf_dc_grad",
-       "sdn_autotune"]
+       "sdn_autotune", "sdn_dcf_estimate"]
 
 # stage names, in the order of the sdn_stage enum
 STAGES = ["pre_fftx", "fft_y", "fft_z", "interp", "clear", "spread", "ifft_z", "ifft_y",
@@ -110,6 +110,7 @@ def lib():
         L.sdn_autotune.argtypes = [ctypes.POINTER(i64), vp, i64, vp, ctypes.c_int32, i32, i32,
                                    ctypes.POINTER(Opts), ctypes.POINTER(Opts),
                                    ctypes.POINTER(ctypes.c_double), vp]
+        L.sdn_dcf_estimate.argtypes = [vp, i32, vp, vp]
         L.sdn_last_error.argtypes = []
         L.sdn_last_error.restype = ctypes.c_char_p
         for name in API:
@@ -317,6 +318,15 @@ def mrf_dc_grad(plan, x, smaps, coil_idx, V, d, w=None, grad=None, loss=None):
                                  _dev(loss, torch.float64, "loss"),
                                  _dev(grad, torch.complex64, "grad"), _stream(x)))
     return loss, grad
+
+
+def dcf_estimate(plan, iterations=10, out=None):
+    """Pipe-Menon density compensation weights [M] (float32, user order)."""
+    if out is None:
+        out = torch.empty(plan.M, dtype=torch.float32, device=plan.device)
+    _check(lib().sdn_dcf_estimate(plan.handle, int(iterations),
+                                  _dev(out, torch.float32, "w") if plan.M else None, _stream(out)))
+    return out
 
 
 TUNED_KEYS = ("tile", "max_points_per_item", "spread_engine")

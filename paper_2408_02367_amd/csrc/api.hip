@@ -404,6 +404,42 @@ sdn_status sdn_mrf_adjoint_plain(sdn_plan p, const void *y, int K, const void *s
   return SDN_OK;
 }
 
+sdn_status sdn_dcf_estimate(sdn_plan p, int iterations, float *w_out, void *stream) {
+  SDN_TRY(check_plan(p, "sdn_dcf_estimate"));
+  if (iterations < 1 || iterations > 1000)
+    return fail(SDN_E_INVALID, "sdn_dcf_estimate: iterations outside 1 .. 1000");
+  if (p->M > 0 && !w_out) return fail(SDN_E_INVALID, "sdn_dcf_estimate: w_out is NULL");
+  if (p->M == 0) return SDN_OK;
+  hipStream_t st = (hipStream_t)stream;
+  SDN_TRY(ensure_grid(p, fine_cells(*p)));
+  SDN_TRY(ensure_part(p, 1, 1));
+  SDN_TRY(ensure_kbuf(p, 2 * (size_t)p->M));
+  float2 *w = p->kbuf, *cw = p->kbuf + p->M;
+  SDN_HIP(launch_dcf_step(w, cw, p->M, true, st), "dcf init");
+  for (int it = 0; it < iterations; ++it) {
+    // C w: spread w onto the fine grid, interpolate it back (no FFT)
+    SpreadArgs s{};
+    s.grid = p->grid;
+    s.part = p->part;
+    s.groups = 1;
+    s.K = 1;
+    s.V = nullptr;
+    s.src = w;
+    s.src_plan_order = false;
+    SDN_STAGE(p, SDN_STAGE_SPREAD, launch_spread(*p, s, st), "dcf spreading");
+    InterpArgs a{};
+    a.grid = p->grid;
+    a.P = 1;
+    a.groups = 1;
+    a.kg = 1;
+    a.y = cw;
+    SDN_STAGE(p, SDN_STAGE_INTERP, launch_interp(*p, a, st), "dcf interpolation");
+    SDN_HIP(launch_dcf_step(w, cw, p->M, false, st), "dcf update");
+  }
+  SDN_HIP(launch_real_part(w, w_out, p->M, st), "dcf output");
+  return SDN_OK;
+}
+
 sdn_status sdn_workspace_size(sdn_plan p, int B, int K, size_t *bytes) {
   SDN_TRY(check_plan(p, "sdn_workspace_size"));
   if (!bytes || B < 1 || K < 1) return fail(SDN_E_INVALID, "sdn_workspace_size: bad argument");

@@ -875,6 +875,41 @@ hipError_t launch_fill_zero(float2 *a, size_t n, hipStream_t st) {
   return hipGetLastError();
 }
 
+namespace {
+// Pipe-Menon step on complex-stored real weights: w <- w / Re(C w); w = 1
+// when first is set.  Imaginary parts stay zero.
+__global__ void k_dcf_step(float2 *w, const float2 *cw, int64_t M, int first) {
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < M;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    if (first) {
+      w[j] = make_float2(1.f, 0.f);
+    } else {
+      w[j] = make_float2(w[j].x / cw[j].x, 0.f);
+    }
+  }
+}
+
+__global__ void k_real_part(const float2 *w, float *out, int64_t M) {
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < M;
+       j += (int64_t)gridDim.x * blockDim.x)
+    out[j] = w[j].x;
+}
+}  // namespace
+
+hipError_t launch_dcf_step(float2 *w, const float2 *cw, int64_t M, bool first, hipStream_t st) {
+  if (M == 0) return hipSuccess;
+  const unsigned blocks = (unsigned)std::min<int64_t>((M + 255) / 256, 1 << 16);
+  hipLaunchKernelGGL(k_dcf_step, dim3(blocks), dim3(256), 0, st, w, cw, M, first ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_real_part(const float2 *w, float *out, int64_t M, hipStream_t st) {
+  if (M == 0) return hipSuccess;
+  const unsigned blocks = (unsigned)std::min<int64_t>((M + 255) / 256, 1 << 16);
+  hipLaunchKernelGGL(k_real_part, dim3(blocks), dim3(256), 0, st, w, out, M);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill_zero_f64(double *a, size_t n, hipStream_t st) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill_zero_f64, dim3(1), dim3(64), 0, st, a, n);

@@ -134,6 +134,10 @@ namespace sdn {
 // (defined in the .hip files; all enqueue on `st`)
 hipError_t launch_fill_zero(float2 *a, size_t n, hipStream_t st);
 hipError_t launch_fill_zero_f64(double *a, size_t n, hipStream_t st);
+// Density compensation: one Pipe-Menon update (or w = 1 when first) and
+// the real parts of complex-stored weights.
+hipError_t launch_dcf_step(float2 *w, const float2 *cw, int64_t M, bool first, hipStream_t st);
+hipError_t launch_real_part(const float2 *w, float *out, int64_t M, hipStream_t st);
 
 // Fine grids are channel-major: P = B K grids [p][nfz][nfy][nfx], p = b K + k.
 // Forward x-pass fused with coil multiply, deapodisation and zero padding.

@@ -92,6 +92,8 @@ typedef struct {
   int64_t max_bin;         /* points in the most populated tile                      */
   int ncoef;               /* coefficients per piece of the kernel polynomial        */
   int64_t nvisit;          /* (point, tile) pairs of the spreading lists             */
+  int spread_engine;       /* engine a call with >= 2 channels per coil uses:
+                              SDN_SPREAD_GATHER or SDN_SPREAD_MATRIX                 */
 } sdn_plan_info;
 
 /* Library defaults: W = 6, sigma = 2, automatic tiles, no budget. */

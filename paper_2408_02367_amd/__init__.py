@@ -63,7 +63,7 @@ class PlanInfo(ctypes.Structure):
                 ("sigma", ctypes.c_double), ("beta", ctypes.c_double),
                 ("tile", ctypes.c_int64 * 3), ("nbins", ctypes.c_int64),
                 ("nwork", ctypes.c_int64), ("max_bin", ctypes.c_int64), ("ncoef", ctypes.c_int),
-                ("nvisit", ctypes.c_int64)]
+                ("nvisit", ctypes.c_int64), ("spread_engine", ctypes.c_int)]
 
 
 _lib = None
@@ -205,7 +205,8 @@ class Plan:
         _check(lib().sdn_plan_get_info(self.handle, ctypes.byref(i)))
         return dict(shape=tuple(i.shape), fine=tuple(i.fine), M=i.M, T=i.T, W=i.W,
                     sigma=i.sigma, beta=i.beta, tile=tuple(i.tile), nbins=i.nbins,
-                    nwork=i.nwork, max_bin=i.max_bin, ncoef=i.ncoef, nvisit=i.nvisit)
+                    nwork=i.nwork, max_bin=i.max_bin, ncoef=i.ncoef, nvisit=i.nvisit,
+                    spread_engine={1: "gather", 2: "matrix"}.get(i.spread_engine, "gather"))
 
     def workspace_size(self, B, K):
         n = ctypes.c_size_t()

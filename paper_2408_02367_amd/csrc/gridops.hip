@@ -794,12 +794,16 @@ hipError_t spread_mma(const SpreadDev &d, int K, dim3 grd, const unsigned *absma
   return hipGetLastError();
 }
 
+}  // namespace
+
 // The matrix-core spreading needs every fine axis >= 16 cells (no support
 // touches both ends of a block) and at least two channels per group.
-bool use_spread_mma(const sdn_plan_s &p, int K) {
+bool spread_engine_for(const sdn_plan_s &p, int K) {
   if (p.spread_engine == SDN_SPREAD_GATHER) return false;
   return K >= 2 && p.ax[0].nf >= 16 && p.ax[1].nf >= 16 && p.ax[2].nf >= 16 && p.absmax != nullptr;
 }
+
+namespace {
 
 template <int W, bool MIX>
 hipError_t spread_k(const SpreadDev &d, int K, dim3 grd, hipStream_t st) {
@@ -837,7 +841,7 @@ hipError_t launch_spread(const sdn_plan_s &p, const SpreadArgs &a, hipStream_t s
   const bool mix = a.V != nullptr;
   dim3 grd((unsigned)p.nsitems, (unsigned)a.groups);
   hipError_t e;
-  if (use_spread_mma(p, a.K)) {
+  if (spread_engine_for(p, a.K)) {
     // value scale: the largest input component (and of V when mixing)
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, p.absmax, 2);
     const size_t nsrc = (size_t)a.groups * (mix ? 1 : a.K) * p.M * 2;

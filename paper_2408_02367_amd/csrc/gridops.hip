@@ -440,49 +440,75 @@ __device__ __forceinline__ float value_scale(const unsigned *absmax, bool mix) {
   return ldexpf(1.f, 14 - e);
 }
 
-// Point data of one list entry, fetched a batch ahead of its use: lanes
-// 0..31 take the x/y half (first node, x and y weights), lanes 32..63 the
-// z/value half (z weights, frame and the input value).
-template <int W>
+// The workgroup takes one block for NG coils, one wave per coil: the point
+// data of a batch (first node, weights) is fetched and staged once for all
+// of them, the four (y,x) operand tiles are built cooperatively into LDS,
+// and each wave builds only its own coil's value operand and products.
+//
+// Point half of a list entry (wave 0; lanes 0..31 the x/y weights and first
+// node, lanes 32..63 the z weights) and value half (lanes 0..31 of every
+// wave: the coil's K values, mixed with conj(V) of the frame when mixing),
+// both fetched a batch ahead of their use.
+template <int W, int K>
 struct MmaFetch {
   int l0;
   float w[2 * W];
-  int frame;
-  float2 v;
+  float2 v[K];
 };
 
-template <int W, bool MIX, int K>
-__device__ __forceinline__ void mma_fetch(const SpreadDev &a, const int4 &it, int grp, int b0,
-                                          int p, int h, MmaFetch<W> &f) {
-  const bool ok = b0 + p < it.z;
-  const int raw = ok ? a.vlist[it.y + b0 + p] : 0;
+__device__ __forceinline__ int mma_point(const SpreadDev &a, const int4 &it, int e) {
+  if (e >= it.z) return -1;
   // a complemented entry is a support that starts in an earlier block (z
   // offset below 0); on grids of at least 16 cells per axis no support
   // meets a block twice, so it is an ordinary entry here
-  const int j = raw < 0 ? ~raw : raw;
-  const float *w = a.wts + (size_t)j * 3 * W;
-  if (h == 0) {
-    f.l0 = __float_as_int(a.rec[j].w);
-#pragma unroll
-    for (int i = 0; i < 2 * W; ++i) f.w[i] = ok ? w[i] : 0.f;
-  } else {
-#pragma unroll
-    for (int i = 0; i < W; ++i) f.w[i] = ok ? w[2 * W + i] : 0.f;
-    const int2 id = a.pidx[j];
-    f.frame = id.x;
-    const int col = a.src_plan ? j : id.y;
-    f.v = ok ? a.src[(size_t)grp * (MIX ? 1 : K) * a.M + col] : make_float2(0.f, 0.f);
-  }
+  const int raw = a.vlist[it.y + e];
+  return raw < 0 ? ~raw : raw;
 }
 
 template <int W, bool MIX, int K>
-__global__ void __launch_bounds__(64) k_spread_mma(SpreadDev a, const unsigned *absmax) {
+__device__ __forceinline__ void mma_fetch(const SpreadDev &a, const int4 &it, int grp, bool coil_ok,
+                                          int b0, int wv, int lane, MmaFetch<W, K> &f) {
+  const int p = lane & (kMmaBatch - 1);
+  const int j = mma_point(a, it, b0 + p);
+  const bool ok = j >= 0;
+  const int jj = ok ? j : 0;
+  const float *w = a.wts + (size_t)jj * 3 * W;
+  if (wv == 0) {
+    const float *wl = w + (lane < kMmaBatch ? 0 : 2 * W);
+#pragma unroll
+    for (int i = 0; i < W; ++i) f.w[i] = ok ? wl[i] : 0.f;
+    if (lane < kMmaBatch) {
+      f.l0 = __float_as_int(a.rec[jj].w);
+#pragma unroll
+      for (int i = 0; i < W; ++i) f.w[W + i] = ok ? wl[W + i] : 0.f;
+    }
+  }
+  if (lane < kMmaBatch) {
+    const bool vok = ok && coil_ok;
+    const int2 id = a.pidx[jj];
+    const int col = a.src_plan ? jj : id.y;
+    if constexpr (MIX) {
+      const float2 r = vok ? a.src[(size_t)grp * a.M + col] : make_float2(0.f, 0.f);
+#pragma unroll
+      for (int k = 0; k < K; ++k) f.v[k] = cmulc(r, a.V[(size_t)id.x * K + k]);
+    } else {
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+        f.v[k] = vok ? a.src[(size_t)(grp * K + k) * a.M + col] : make_float2(0.f, 0.f);
+    }
+  }
+}
+
+template <int W, bool MIX, int K, int NG>
+__global__ void __launch_bounds__(64 * NG) k_spread_mma(SpreadDev a, const unsigned *absmax) {
   __shared__ float wrow[3][kMmaBatch][kWinLen];
-  __shared__ float vals[kMmaBatch][2 * K + 1];
+  __shared__ float vals[NG][kMmaBatch][2 * K + 1];
   __shared__ int shifts[kMmaBatch];
+  __shared__ uint4 sA[2][4][64];   // (y,x) operand fragments: hi/lo, row tile, lane
   const int4 it = a.items[blockIdx.x];
-  const int grp = blockIdx.y;
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  const int grp = blockIdx.y * NG + wv;
+  const bool coil_ok = grp < a.groups;
   const int bzi = it.x / (a.nbx * a.nby);
   const int rem = it.x - bzi * (a.nbx * a.nby);
   const int byi = rem / a.nbx, bxi = rem - byi * a.nbx;
@@ -490,7 +516,7 @@ __global__ void __launch_bounds__(64) k_spread_mma(SpreadDev a, const unsigned *
   const float s = value_scale(absmax, MIX);
 
   // zero the weight rows once; each batch rewrites only the W weights
-  for (int i = lane; i < 3 * kMmaBatch * kWinLen; i += 64) (&wrow[0][0][0])[i] = 0.f;
+  for (int i = tid; i < 3 * kMmaBatch * kWinLen; i += 64 * NG) (&wrow[0][0][0])[i] = 0.f;
 
   sdn_float4v acc[4][K];
 #pragma unroll
@@ -499,77 +525,77 @@ __global__ void __launch_bounds__(64) k_spread_mma(SpreadDev a, const unsigned *
     for (int k = 0; k < K; ++k) acc[t][k] = sdn_float4v{0.f, 0.f, 0.f, 0.f};
 
   const int p = lane & (kMmaBatch - 1);   // fetch: this lane's entry
-  const int h = lane / kMmaBatch;         // 0: x/y half, 1: z/value half
   const int r16 = lane & 15;              // fragment row (A) / column (B)
   const int e0 = 8 * (lane >> 4);         // fragment entries e0 .. e0+7
   const int fx = r16 & 7, fy = r16 >> 3;  // A: x and y offset of the row
   const int fz = r16 & 7, fri = r16 >> 3; // B: z and re/im of the column
 
-  MmaFetch<W> f;
-  if (it.z > 0) mma_fetch<W, MIX, K>(a, it, grp, 0, p, h, f);
+  MmaFetch<W, K> f;
+  if (it.z > 0) mma_fetch<W, MIX, K>(a, it, grp, coil_ok, 0, wv, lane, f);
   for (int b0 = 0; b0 < it.z; b0 += kMmaBatch) {
     __syncthreads();
-    // stage this batch's point data
-    if (h == 0) {
-      const unsigned u = (unsigned)f.l0;
-      const int sx = win_shift(ox, (int)(u & 1023u), a.nfx, W);
-      const int sy = win_shift(oy, (int)((u >> 10) & 1023u), a.nfy, W);
-      const int sz = win_shift(oz, (int)((u >> 20) & 1023u), a.nfz, W);
-      shifts[p] = (sx + kWinPad) | ((sy + kWinPad) << 8) | ((sz + kWinPad) << 16);
+    // stage this batch: point data (wave 0) and each coil's values
+    if (wv == 0) {
+      if (lane < kMmaBatch) {
+        const unsigned u = (unsigned)f.l0;
+        const int sx = win_shift(ox, (int)(u & 1023u), a.nfx, W);
+        const int sy = win_shift(oy, (int)((u >> 10) & 1023u), a.nfy, W);
+        const int sz = win_shift(oz, (int)((u >> 20) & 1023u), a.nfz, W);
+        shifts[p] = (sx + kWinPad) | ((sy + kWinPad) << 8) | ((sz + kWinPad) << 16);
 #pragma unroll
-      for (int i = 0; i < W; ++i) {
-        wrow[0][p][kWinPad + i] = f.w[i];
-        wrow[1][p][kWinPad + i] = f.w[W + i];
-      }
-    } else {
-#pragma unroll
-      for (int i = 0; i < W; ++i) wrow[2][p][kWinPad + i] = f.w[i];
-      if constexpr (MIX) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-          const float2 v = cmulc(f.v, a.V[(size_t)f.frame * K + k]);
-          vals[p][2 * k] = v.x * s;
-          vals[p][2 * k + 1] = v.y * s;
+        for (int i = 0; i < W; ++i) {
+          wrow[0][p][kWinPad + i] = f.w[i];
+          wrow[1][p][kWinPad + i] = f.w[W + i];
         }
       } else {
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-          const bool ok = b0 + p < it.z;
-          const int raw = ok ? a.vlist[it.y + b0 + p] : 0;
-          const int j = raw < 0 ? ~raw : raw;
-          const int col = a.src_plan ? j : a.pidx[j].y;
-          const float2 v = ok ? a.src[(size_t)(grp * K + k) * a.M + col] : make_float2(0.f, 0.f);
-          vals[p][2 * k] = v.x * s;
-          vals[p][2 * k + 1] = v.y * s;
-        }
+        for (int i = 0; i < W; ++i) wrow[2][p][kWinPad + i] = f.w[i];
+      }
+    }
+    if (lane < kMmaBatch) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        vals[wv][p][2 * k] = f.v[k].x * s;
+        vals[wv][p][2 * k + 1] = f.v[k].y * s;
       }
     }
     // the next batch's point data is in flight during this batch's products
-    if (b0 + kMmaBatch < it.z) mma_fetch<W, MIX, K>(a, it, grp, b0 + kMmaBatch, p, h, f);
+    if (b0 + kMmaBatch < it.z) mma_fetch<W, MIX, K>(a, it, grp, coil_ok, b0 + kMmaBatch, wv, lane, f);
     __syncthreads();
-    // fragments straight into registers: A[(y,x)][e] = wy wx, B[e][(re/im,z)] = wz v
-    float ax[4][8], bz[8];
+    // (y,x) operand tiles, shared by the coils: wave wv builds tiles wv, wv+NG, ...
+#pragma unroll
+    for (int t0 = 0; t0 < 4; t0 += NG) {
+      const int t = t0 + wv;
+      if (NG * ((4 + NG - 1) / NG) == 4 || t < 4) {
+        float ax[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int q = e0 + e;
+          const int sh = shifts[q];
+          ax[e] = wrow[1][q][((sh >> 8) & 255) + 2 * t + fy] * wrow[0][q][(sh & 255) + fx];
+        }
+        unsigned hi[4], lo[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) split2(ax[2 * e], ax[2 * e + 1], hi[e], lo[e]);
+        sA[0][t][lane] = make_uint4(hi[0], hi[1], hi[2], hi[3]);
+        sA[1][t][lane] = make_uint4(lo[0], lo[1], lo[2], lo[3]);
+      }
+    }
+    // this coil's value operand: B[e][(re/im, z)] = wz v
     float bvv[K][8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int q = e0 + e;
-      const int sh = shifts[q];
-      const int sx = sh & 255, sy = (sh >> 8) & 255, sz = (sh >> 16) & 255;
-      const float wxv = wrow[0][q][sx + fx];
+      const float bz = wrow[2][q][((shifts[q] >> 16) & 255) + fz];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) ax[t][e] = wrow[1][q][sy + 2 * t + fy] * wxv;
-      bz[e] = wrow[2][q][sz + fz];
-#pragma unroll
-      for (int k = 0; k < K; ++k) bvv[k][e] = bz[e] * vals[q][2 * k + fri];
+      for (int k = 0; k < K; ++k) bvv[k][e] = bz * vals[wv][q][2 * k + fri];
     }
+    __syncthreads();
     sdn_half8 ah[4], al[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      unsigned hi[4], lo[4];
-#pragma unroll
-      for (int e = 0; e < 4; ++e) split2(ax[t][2 * e], ax[t][2 * e + 1], hi[e], lo[e]);
-      ah[t] = __builtin_bit_cast(sdn_half8, make_uint4(hi[0], hi[1], hi[2], hi[3]));
-      al[t] = __builtin_bit_cast(sdn_half8, make_uint4(lo[0], lo[1], lo[2], lo[3]));
+      ah[t] = __builtin_bit_cast(sdn_half8, sA[0][t][lane]);
+      al[t] = __builtin_bit_cast(sdn_half8, sA[1][t][lane]);
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -586,6 +612,7 @@ __global__ void __launch_bounds__(64) k_spread_mma(SpreadDev a, const unsigned *
       }
     }
   }
+  if (!coil_ok) return;
   // lane holds rows (y,x) = 16t + 4(lane/16) + i, column (re/im, z) = lane % 16
   const float inv = 1.f / s;
   const int ri = (lane >> 3) & 1, z = lane & 7;
@@ -784,10 +811,17 @@ size_t spread_part_elems(const sdn_plan_s &p, int groups, int K) {
 namespace {
 template <int W, bool MIX>
 hipError_t spread_mma(const SpreadDev &d, int K, dim3 grd, const unsigned *absmax, hipStream_t st) {
-  switch (K) {
-#define SDN_SPM(KV) \
-  case KV: hipLaunchKernelGGL((k_spread_mma<W, MIX, KV>), grd, dim3(64), 0, st, d, absmax); break;
-    SDN_SPM(2) SDN_SPM(3) SDN_SPM(4) SDN_SPM(5) SDN_SPM(6) SDN_SPM(7) SDN_SPM(8)
+  // up to four coils per workgroup, one wave each
+  const int ng = std::min(d.groups, 4);
+  grd.y = (unsigned)((d.groups + ng - 1) / ng);
+  switch (K * 8 + ng) {
+#define SDN_SPM(KV, NGV)                                                                 \
+  case KV * 8 + NGV:                                                                     \
+    hipLaunchKernelGGL((k_spread_mma<W, MIX, KV, NGV>), grd, dim3(64 * NGV), 0, st, d, absmax); \
+    break;
+#define SDN_SPM4(KV) SDN_SPM(KV, 1) SDN_SPM(KV, 2) SDN_SPM(KV, 3) SDN_SPM(KV, 4)
+    SDN_SPM4(2) SDN_SPM4(3) SDN_SPM4(4) SDN_SPM4(5) SDN_SPM4(6) SDN_SPM4(7) SDN_SPM4(8)
+#undef SDN_SPM4
 #undef SDN_SPM
     default: return hipErrorInvalidValue;
   }

@@ -206,6 +206,7 @@ __global__ void __launch_bounds__(kIThreads) k_interp(InterpDev a) {
 struct SpreadDev {
   const int4 *items;   // (block, list start, count, partial slot or -1)
   const int *vlist;
+  const int2 *vinfo;   // per list entry: (frame, original index); matrix-core engine
   const float4 *rec;
   const int2 *pidx;
   const float *wts;    // per point: W weights for x, y, z
@@ -445,53 +446,70 @@ __device__ __forceinline__ float value_scale(const unsigned *absmax, bool mix) {
 // of them, the four (y,x) operand tiles are built cooperatively into LDS,
 // and each wave builds only its own coil's value operand and products.
 //
-// Point half of a list entry (wave 0; lanes 0..31 the x/y weights and first
-// node, lanes 32..63 the z weights) and value half (lanes 0..31 of every
-// wave: the coil's K values, mixed with conj(V) of the frame when mixing),
-// both fetched a batch ahead of their use.
-template <int W, int K>
-struct MmaFetch {
-  int l0;
-  float w[2 * W];
-  float2 v[K];
+// Each entry goes through two fetch stages, so that no load waits on
+// another load issued in the same batch: the list stage (two batches
+// ahead) reads the entry and its (frame, original index); the point stage
+// (one batch ahead) reads, through those, the point's first node and
+// weights (wave 0; lanes 0..31 the x/y weights and the node, lanes 32..63
+// the z weights) and its values: with mixing, every wave the residual of
+// its coil (lanes 0..31) and the last wave the frame's K basis values for
+// all coils (each half-wave a half of them); else every wave the K values
+// of its coil.  A load instruction costs the memory pipeline about one
+// cycle per cache line it touches, so each scattered value is loaded once
+// per workgroup, not once per coil.
+struct MmaList {
+  int j;      // plan index of the point
+  int2 id;    // (frame, original index)
+  bool ok;
 };
 
-__device__ __forceinline__ int mma_point(const SpreadDev &a, const int4 &it, int e) {
-  if (e >= it.z) return -1;
+template <int W, bool MIX, int K>
+struct MmaFetch {
+  static constexpr int NV = MIX ? (K + 1) / 2 : K;
+  int l0;
+  float w[2 * W];
+  float2 r;
+  float2 v[NV];
+};
+
+__device__ __forceinline__ void mma_list(const SpreadDev &a, const int4 &it, int e, bool all_lanes,
+                                         int lane, MmaList &L) {
+  L.ok = e < it.z;
+  const int raw = L.ok ? a.vlist[it.y + e] : 0;
   // a complemented entry is a support that starts in an earlier block (z
   // offset below 0); on grids of at least 16 cells per axis no support
   // meets a block twice, so it is an ordinary entry here
-  const int raw = a.vlist[it.y + e];
-  return raw < 0 ? ~raw : raw;
+  L.j = raw < 0 ? ~raw : raw;
+  L.id = (L.ok && (all_lanes || lane < kMmaBatch)) ? a.vinfo[it.y + e] : make_int2(0, 0);
 }
 
 template <int W, bool MIX, int K>
-__device__ __forceinline__ void mma_fetch(const SpreadDev &a, const int4 &it, int grp, bool coil_ok,
-                                          int b0, int wv, int lane, MmaFetch<W, K> &f) {
-  const int p = lane & (kMmaBatch - 1);
-  const int j = mma_point(a, it, b0 + p);
-  const bool ok = j >= 0;
-  const int jj = ok ? j : 0;
-  const float *w = a.wts + (size_t)jj * 3 * W;
+__device__ __forceinline__ void mma_fetch(const SpreadDev &a, const MmaList &L, int grp, bool coil_ok,
+                                          bool v_wave, int wv, int lane, MmaFetch<W, MIX, K> &f) {
+  const bool ok = L.ok;
+  const float *w = a.wts + (size_t)L.j * 3 * W;
   if (wv == 0) {
     const float *wl = w + (lane < kMmaBatch ? 0 : 2 * W);
 #pragma unroll
     for (int i = 0; i < W; ++i) f.w[i] = ok ? wl[i] : 0.f;
     if (lane < kMmaBatch) {
-      f.l0 = __float_as_int(a.rec[jj].w);
+      f.l0 = __float_as_int(a.rec[L.j].w);
 #pragma unroll
       for (int i = 0; i < W; ++i) f.w[W + i] = ok ? wl[W + i] : 0.f;
     }
   }
-  if (lane < kMmaBatch) {
-    const bool vok = ok && coil_ok;
-    const int2 id = a.pidx[jj];
-    const int col = a.src_plan ? jj : id.y;
-    if constexpr (MIX) {
-      const float2 r = vok ? a.src[(size_t)grp * a.M + col] : make_float2(0.f, 0.f);
+  const bool vok = ok && coil_ok;
+  const int col = a.src_plan ? L.j : L.id.y;
+  if constexpr (MIX) {
+    if (lane < kMmaBatch) f.r = vok ? a.src[(size_t)grp * a.M + col] : make_float2(0.f, 0.f);
+    if (v_wave) {
+      const int k0 = (lane >> 5) * f.NV;
 #pragma unroll
-      for (int k = 0; k < K; ++k) f.v[k] = cmulc(r, a.V[(size_t)id.x * K + k]);
-    } else {
+      for (int i = 0; i < f.NV; ++i)
+        f.v[i] = k0 + i < K ? a.V[(size_t)L.id.x * K + k0 + i] : make_float2(0.f, 0.f);
+    }
+  } else {
+    if (lane < kMmaBatch) {
 #pragma unroll
       for (int k = 0; k < K; ++k)
         f.v[k] = vok ? a.src[(size_t)(grp * K + k) * a.M + col] : make_float2(0.f, 0.f);
@@ -501,14 +519,21 @@ __device__ __forceinline__ void mma_fetch(const SpreadDev &a, const int4 &it, in
 
 template <int W, bool MIX, int K, int NG>
 __global__ void __launch_bounds__(64 * NG) k_spread_mma(SpreadDev a, const unsigned *absmax) {
-  __shared__ float wrow[3][kMmaBatch][kWinLen];
-  __shared__ float vals[NG][kMmaBatch][2 * K + 1];
-  __shared__ int shifts[kMmaBatch];
-  __shared__ uint4 sA[2][4][64];   // (y,x) operand fragments: hi/lo, row tile, lane
+  // values per entry and coil: [re/im][k], K padded to even so that a lane
+  // reads its component's K values with 8-byte loads
+  constexpr int KP = (K + 1) & ~1;
+  // double-buffered staging: batch n is read from buffer n & 1 while batch
+  // n + 1 is written to the other, so one barrier per batch suffices
+  __shared__ float wrow[2][3][kMmaBatch][kWinLen];
+  __shared__ __align__(16) float vals[2][NG][kMmaBatch][2 * KP];
+  __shared__ __align__(16) float2 vbas[2][kMmaBatch][KP];   // mixing: the frame's basis values
+  __shared__ int shifts[2][kMmaBatch];
+  __shared__ uint4 sA[2][2][4][64];   // [buffer][hi/lo][row tile][lane]: (y,x) operand fragments
   const int4 it = a.items[blockIdx.x];
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
   const int grp = blockIdx.y * NG + wv;
   const bool coil_ok = grp < a.groups;
+  const bool v_wave = MIX && wv == NG - 1;   // loads the basis values for all coils
   const int bzi = it.x / (a.nbx * a.nby);
   const int rem = it.x - bzi * (a.nbx * a.nby);
   const int byi = rem / a.nbx, bxi = rem - byi * a.nbx;
@@ -516,7 +541,7 @@ __global__ void __launch_bounds__(64 * NG) k_spread_mma(SpreadDev a, const unsig
   const float s = value_scale(absmax, MIX);
 
   // zero the weight rows once; each batch rewrites only the W weights
-  for (int i = tid; i < 3 * kMmaBatch * kWinLen; i += 64 * NG) (&wrow[0][0][0])[i] = 0.f;
+  for (int i = tid; i < 2 * 3 * kMmaBatch * kWinLen; i += 64 * NG) (&wrow[0][0][0][0])[i] = 0.f;
 
   sdn_float4v acc[4][K];
 #pragma unroll
@@ -530,38 +555,84 @@ __global__ void __launch_bounds__(64 * NG) k_spread_mma(SpreadDev a, const unsig
   const int fx = r16 & 7, fy = r16 >> 3;  // A: x and y offset of the row
   const int fz = r16 & 7, fri = r16 >> 3; // B: z and re/im of the column
 
-  MmaFetch<W, K> f;
-  if (it.z > 0) mma_fetch<W, MIX, K>(a, it, grp, coil_ok, 0, wv, lane, f);
-  for (int b0 = 0; b0 < it.z; b0 += kMmaBatch) {
-    __syncthreads();
-    // stage this batch: point data (wave 0) and each coil's values
+  MmaList L;
+  MmaFetch<W, MIX, K> f;
+  float2 r_staged = make_float2(0.f, 0.f);   // mixing: residual of the staged batch
+  // stage the fetched batch into buffer bf: wave 0 the point data; with
+  // mixing the basis values (last wave), else every wave its coil's values
+  auto stage = [&](int bf) {
     if (wv == 0) {
       if (lane < kMmaBatch) {
         const unsigned u = (unsigned)f.l0;
         const int sx = win_shift(ox, (int)(u & 1023u), a.nfx, W);
         const int sy = win_shift(oy, (int)((u >> 10) & 1023u), a.nfy, W);
         const int sz = win_shift(oz, (int)((u >> 20) & 1023u), a.nfz, W);
-        shifts[p] = (sx + kWinPad) | ((sy + kWinPad) << 8) | ((sz + kWinPad) << 16);
+        shifts[bf][p] = (sx + kWinPad) | ((sy + kWinPad) << 8) | ((sz + kWinPad) << 16);
 #pragma unroll
         for (int i = 0; i < W; ++i) {
-          wrow[0][p][kWinPad + i] = f.w[i];
-          wrow[1][p][kWinPad + i] = f.w[W + i];
+          wrow[bf][0][p][kWinPad + i] = f.w[i];
+          wrow[bf][1][p][kWinPad + i] = f.w[W + i];
         }
       } else {
 #pragma unroll
-        for (int i = 0; i < W; ++i) wrow[2][p][kWinPad + i] = f.w[i];
+        for (int i = 0; i < W; ++i) wrow[bf][2][p][kWinPad + i] = f.w[i];
       }
     }
-    if (lane < kMmaBatch) {
+    if constexpr (MIX) {
+      if (v_wave) {
+        const int k0 = (lane >> 5) * f.NV;
 #pragma unroll
-      for (int k = 0; k < K; ++k) {
-        vals[wv][p][2 * k] = f.v[k].x * s;
-        vals[wv][p][2 * k + 1] = f.v[k].y * s;
+        for (int i = 0; i < f.NV; ++i)
+          if (k0 + i < K) vbas[bf][p][k0 + i] = f.v[i];
+      }
+      r_staged = f.r;
+    } else {
+      if (lane < kMmaBatch) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          vals[bf][wv][p][k] = f.v[k].x * s;
+          vals[bf][wv][p][KP + k] = f.v[k].y * s;
+        }
       }
     }
-    // the next batch's point data is in flight during this batch's products
-    if (b0 + kMmaBatch < it.z) mma_fetch<W, MIX, K>(a, it, grp, coil_ok, b0 + kMmaBatch, wv, lane, f);
-    __syncthreads();
+  };
+  // mixing, after the barrier that published the basis values: this coil's
+  // values r conj(V_k), written and later read by this wave only
+  auto mix_values = [&](int bf) {
+    if constexpr (MIX) {
+      if (lane < kMmaBatch) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const float2 v = cmulc(r_staged, vbas[bf][p][k]);
+          vals[bf][wv][p][k] = v.x * s;
+          vals[bf][wv][p][KP + k] = v.y * s;
+        }
+      }
+    }
+  };
+  // the fetch pipeline: the point data one batch ahead of its staging, the
+  // list two batches ahead
+  auto advance = [&](int e) {
+    if (e < it.z) {
+      mma_fetch<W, MIX, K>(a, L, grp, coil_ok, v_wave, wv, lane, f);
+      if (e + kMmaBatch < it.z) mma_list(a, it, e + kMmaBatch + p, v_wave, lane, L);
+    }
+  };
+
+  if (it.z > 0) {
+    mma_list(a, it, p, v_wave, lane, L);
+    mma_fetch<W, MIX, K>(a, L, grp, coil_ok, v_wave, wv, lane, f);
+    if (kMmaBatch < it.z) mma_list(a, it, kMmaBatch + p, v_wave, lane, L);
+  }
+  __syncthreads();   // rows zeroed
+  if (it.z > 0) {
+    stage(0);
+    advance(kMmaBatch);
+  }
+  __syncthreads();
+  mix_values(0);
+  int bf = 0;
+  for (int b0 = 0; b0 < it.z; b0 += kMmaBatch, bf ^= 1) {
     // (y,x) operand tiles, shared by the coils: wave wv builds tiles wv, wv+NG, ...
 #pragma unroll
     for (int t0 = 0; t0 < 4; t0 += NG) {
@@ -571,14 +642,14 @@ __global__ void __launch_bounds__(64 * NG) k_spread_mma(SpreadDev a, const unsig
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
           const int q = e0 + e;
-          const int sh = shifts[q];
-          ax[e] = wrow[1][q][((sh >> 8) & 255) + 2 * t + fy] * wrow[0][q][(sh & 255) + fx];
+          const int sh = shifts[bf][q];
+          ax[e] = wrow[bf][1][q][((sh >> 8) & 255) + 2 * t + fy] * wrow[bf][0][q][(sh & 255) + fx];
         }
         unsigned hi[4], lo[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) split2(ax[2 * e], ax[2 * e + 1], hi[e], lo[e]);
-        sA[0][t][lane] = make_uint4(hi[0], hi[1], hi[2], hi[3]);
-        sA[1][t][lane] = make_uint4(lo[0], lo[1], lo[2], lo[3]);
+        sA[bf][0][t][lane] = make_uint4(hi[0], hi[1], hi[2], hi[3]);
+        sA[bf][1][t][lane] = make_uint4(lo[0], lo[1], lo[2], lo[3]);
       }
     }
     // this coil's value operand: B[e][(re/im, z)] = wz v
@@ -586,16 +657,28 @@ __global__ void __launch_bounds__(64 * NG) k_spread_mma(SpreadDev a, const unsig
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int q = e0 + e;
-      const float bz = wrow[2][q][((shifts[q] >> 16) & 255) + fz];
+      const float bz = wrow[bf][2][q][((shifts[bf][q] >> 16) & 255) + fz];
+      const float2 *vr = reinterpret_cast<const float2 *>(&vals[bf][wv][q][fri * KP]);
 #pragma unroll
-      for (int k = 0; k < K; ++k) bvv[k][e] = bz * vals[wv][q][2 * k + fri];
+      for (int k2 = 0; k2 < KP / 2; ++k2) {
+        const float2 v = vr[k2];
+        bvv[2 * k2][e] = bz * v.x;
+        if (2 * k2 + 1 < K) bvv[2 * k2 + 1][e] = bz * v.y;
+      }
+    }
+    // the next batch goes to the other buffer while this one is in use
+    const bool more = b0 + kMmaBatch < it.z;
+    if (more) {
+      stage(bf ^ 1);
+      advance(b0 + 2 * kMmaBatch);
     }
     __syncthreads();
+    if (more) mix_values(bf ^ 1);
     sdn_half8 ah[4], al[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      ah[t] = __builtin_bit_cast(sdn_half8, sA[0][t][lane]);
-      al[t] = __builtin_bit_cast(sdn_half8, sA[1][t][lane]);
+      ah[t] = __builtin_bit_cast(sdn_half8, sA[bf][0][t][lane]);
+      al[t] = __builtin_bit_cast(sdn_half8, sA[bf][1][t][lane]);
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -834,7 +917,8 @@ hipError_t spread_mma(const SpreadDev &d, int K, dim3 grd, const unsigned *absma
 // touches both ends of a block) and at least two channels per group.
 bool spread_engine_for(const sdn_plan_s &p, int K) {
   if (p.spread_engine == SDN_SPREAD_GATHER) return false;
-  return K >= 2 && p.ax[0].nf >= 16 && p.ax[1].nf >= 16 && p.ax[2].nf >= 16 && p.absmax != nullptr;
+  return K >= 2 && p.ax[0].nf >= 16 && p.ax[1].nf >= 16 && p.ax[2].nf >= 16 &&
+         p.absmax != nullptr && (p.vinfo != nullptr || p.nvisit == 0);
 }
 
 namespace {
@@ -859,6 +943,7 @@ hipError_t launch_spread(const sdn_plan_s &p, const SpreadArgs &a, hipStream_t s
   SpreadDev d;
   d.items = p.sitems;
   d.vlist = p.vlist;
+  d.vinfo = p.vinfo;
   d.rec = p.rec;
   d.pidx = p.pidx;
   d.wts = p.wts;

@@ -193,6 +193,15 @@ __global__ void k_visit_count(const float4 *__restrict__ rec, int M, FoldGeom g,
   per_point[j] = vz.n * ny * nx;
 }
 
+// (frame, original index) of every list entry's point, in list order.
+__global__ void k_visit_info(const int *__restrict__ vlist, int n, const int2 *__restrict__ pidx,
+                             int2 *__restrict__ vinfo) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int raw = vlist[i];
+  vinfo[i] = pidx[raw < 0 ? ~raw : raw];
+}
+
 // Pass 2: (block, offset) key and entry of every visit, at the point's
 // position of the exclusive scan of pass 1 (so in plan order).
 __global__ void k_visit_pairs(const float4 *__restrict__ rec, int M, FoldGeom g,
@@ -297,6 +306,8 @@ void free_plan_memory(sdn_plan_s *p) {
   if (p->frame_user) (void)hipFree(p->frame_user);
   if (p->work) (void)hipFree(p->work);
   if (p->vlist) (void)hipFree(p->vlist);
+  if (p->vinfo) (void)hipFree(p->vinfo);
+  p->vinfo = nullptr;
   if (p->wts) (void)hipFree(p->wts);
   p->wts = nullptr;
   if (p->sitems) (void)hipFree(p->sitems);
@@ -609,6 +620,18 @@ sdn_status sdn_plan_create(sdn_plan *out, const int64_t shape[3], const float *t
       if (s == SDN_OK)
         s = sort_pairs(vkey, vkey2, vval, p->vlist, nv,
                        key_bits((uint64_t)nsb * kVisitOffsets), st);
+      // the matrix-core engine reads each entry's frame and original index
+      // beside the list; the gather engine does without
+      const bool matrix_ok = p->spread_engine != SDN_SPREAD_GATHER && p->ax[0].nf >= 16 &&
+                             p->ax[1].nf >= 16 && p->ax[2].nf >= 16;
+      if (s == SDN_OK && matrix_ok) {
+        s = dalloc(&p->vinfo, nv, "plan spreading lists");
+        if (s == SDN_OK) {
+          hipLaunchKernelGGL(k_visit_info, dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, st,
+                             p->vlist, nv, p->pidx, p->vinfo);
+          s = hip_check(hipGetLastError(), "plan visit info kernel");
+        }
+      }
     }
     if (s == SDN_OK) s = hip_check(hipStreamSynchronize(st), "plan sync");
   }

@@ -98,6 +98,8 @@ struct sdn_plan_s {
   float *wts = nullptr;      // per point (plan order): W weights per axis, x then y then z
   int *vlist = nullptr;      // spreading lists: plan indices of the points whose support
                              // touches a spreading block, grouped by block
+  int2 *vinfo = nullptr;     // per list entry, matrix-core engine only: (frame, original
+                             // index) of its point, so that a value fetch needs no pidx hop
   int4 *sitems = nullptr;    // spreading items: (block, list start, count, partial slot or -1)
   int4 *splits = nullptr;    // crowded blocks: (block, first slot, slots, 0)
   int64_t nsbins = 0;        // spreading blocks

@@ -22,10 +22,15 @@ What it computes (Sec. 2, Eq. 1-3 of the paper):
                  frame-expansion brute force for tiny sizes.
 * ``dcf``      - the density compensation weights of Eq. 2 by Pipe-Menon
                  fixed-point iteration with the gridding kernel.
+* ``tv``       - the total-variation penalty of Alg. 1 (StoDIP + TV) and its
+                 gradient.
+* ``recon``    - the initialisers of Sec. 2.3: normal operator over all
+                 coils, conjugate gradients (with and without Tikhonov) and
+                 the scaled adjoint.
 
 Every function is pinned by the ``-m "not gpu"`` tests in ``tests/`` to
 something other than itself (library FFTs on on-grid points, closed forms,
 Parseval, adjoint identities, quadrature, brute-force loops).
 """
 
-from . import nudft, kernel, gridding, mrf, dcf  # noqa: F401
+from . import nudft, kernel, gridding, mrf, dcf, tv, recon  # noqa: F401

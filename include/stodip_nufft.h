@@ -237,6 +237,73 @@ SDN_API sdn_status sdn_mrf_adjoint_plain(sdn_plan plan, const void *y, int K, co
 SDN_API sdn_status sdn_dcf_estimate(sdn_plan plan, int iterations, float *w_out, void *stream);
 
 /*
+ * Initialisers of the TSMI x^(0) (Sec. 2.3 starts the network from an
+ * estimate of the inverse problem of Eq. 1: the SVD-MRF adjoint with a
+ * scaling factor, and low-rank least squares by conjugate gradients, with
+ * or without Tikhonov regularisation).  The paper names the three only;
+ * the operators here, over the B listed coils with the DCF weight
+ * W = diag(w) of Eq. 2 (w NULL: 1):
+ *
+ *   normal operator  N x = sum_b A_b^H W A_b x + lambda x
+ *   data term        b   = sum_b A_b^H W y_b
+ *
+ * Arguments as for sdn_mrf_dc_grad; y: dev complex64 [B][M] user order,
+ * row b the samples of coil coil_idx[b] (all C coils for a full solve);
+ * lambda >= 0 and finite.  Image vectors are dev complex64 [K][Nz][Ny][Nx].
+ * Coils go through the stages in chunks that fit the workspace budget.
+ *
+ * sdn_mrf_normal:  out = N x (overwritten).
+ * sdn_mrf_cg:      x holds the start point on entry and the result after
+ *                  `iterations` (0 .. 100000) conjugate-gradient steps on
+ *                  N x = b (Hestenes-Stiefel).  history: dev double
+ *                  [iterations + 1] or NULL; entry i is |b - N x_i|^2.
+ *                  Every scalar of the iteration is formed on the device
+ *                  (FP64 sums in a fixed order), so the whole solve is
+ *                  enqueued without a host round trip.  A zero curvature
+ *                  or residual gives a zero step (the iteration stalls
+ *                  instead of producing NaN).  Uses 3 image vectors of
+ *                  plan workspace beside the grids.
+ * sdn_mrf_scaled_adjoint: x_out = s z with z = b and the least-squares
+ *                  scale s = |z|^2 / sum_b <A_b z, W A_b z> (0 if the
+ *                  denominator is 0); scale: dev double [1] receiving s,
+ *                  or NULL.
+ * Errors: as sdn_mrf_dc_grad; SDN_E_INVALID for a negative or non-finite
+ * lambda or an iteration count outside the range.
+ */
+SDN_API sdn_status sdn_mrf_normal(sdn_plan plan, const void *x, int K, const void *smaps, int C,
+                                  const int32_t *coil_idx, int B, const void *V, const float *w,
+                                  float lambda, void *out, void *stream);
+SDN_API sdn_status sdn_mrf_cg(sdn_plan plan, const void *y, int K, const void *smaps, int C,
+                              const int32_t *coil_idx, int B, const void *V, const float *w,
+                              float lambda, int iterations, void *x, double *history,
+                              void *stream);
+SDN_API sdn_status sdn_mrf_scaled_adjoint(sdn_plan plan, const void *y, int K, const void *smaps,
+                                          int C, const int32_t *coil_idx, int B, const void *V,
+                                          const float *w, void *x_out, double *scale,
+                                          void *stream);
+
+/*
+ * Total-variation penalty of Alg. 1 (the StoDIP + TV variant adds lambda
+ * TV(x_hat) to the per-coil loss; Sec. 2.2 does not define the TV form).
+ * The form computed: isotropic over the three spatial axes, per channel,
+ * forward differences that are zero at the last index of an axis, and a
+ * smoothing eps > 0:
+ *   TV(x) = sum_k sum_n sqrt(|D_x x_k[n]|^2 + |D_y x_k[n]|^2 + |D_z x_k[n]|^2 + eps^2)
+ * on the plan's image shape.
+ *   x      dev complex64 [K][Nz][Ny][Nx]
+ *   value  dev double [1] receiving lambda TV(x) (FP64 sum in a fixed
+ *          order), or NULL
+ *   grad   dev complex64 [K][Nz][Ny][Nx] receiving lambda dTV/dRe x +
+ *          i lambda dTV/dIm x (added to its contents when accumulate is
+ *          non-zero, so it can follow sdn_mrf_dc_grad), or NULL
+ * One fused stencil pass; uses plan scratch of one double per 256 voxels.
+ * Errors: SDN_E_INVALID for a null x, both outputs NULL, K outside [1, 8],
+ * eps not finite and > 0, or lambda negative or not finite.
+ */
+SDN_API sdn_status sdn_tv_grad(sdn_plan plan, const void *x, int K, float eps, float lambda,
+                               double *value, void *grad, int accumulate, void *stream);
+
+/*
  * Autotuner: builds candidate plans for one trajectory (interpolation tile
  * edge 16x16x8 / 8 / 16, up to 2048 or 1024 points per work item, gather or
  * matrix-core spreading, all other options from `base`), times three

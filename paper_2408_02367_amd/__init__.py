@@ -35,7 +35,8 @@ API = ["sdn_default_opts", "sdn_plan_create", "sdn_plan_destroy", "sdn_plan_get_
        "sdn_release_workspace", "sdn_profile_enable", "sdn_profile_read",
        "sdn_kernel_tables", "sdn_last_error", "sdn_group_create", "sdn_group_destroy",
        "sdn_group_mrf_forward", "sdn_group_mrf_adjoint", "sdn_group_mrf_dc_grad",
-       "sdn_autotune", "sdn_dcf_estimate"]
+       "sdn_autotune", "sdn_dcf_estimate", "sdn_mrf_normal", "sdn_mrf_cg",
+       "sdn_mrf_scaled_adjoint", "sdn_tv_grad"]
 
 # stage names, in the order of the sdn_stage enum
 STAGES = ["pre_fftx", "fft_y", "fft_z", "interp", "clear", "spread", "ifft_z", "ifft_y",
@@ -111,6 +112,14 @@ def lib():
                                    ctypes.POINTER(Opts), ctypes.POINTER(Opts),
                                    ctypes.POINTER(ctypes.c_double), vp]
         L.sdn_dcf_estimate.argtypes = [vp, i32, vp, vp]
+        f32 = ctypes.c_float
+        L.sdn_mrf_normal.argtypes = [vp, vp, i32, vp, i32, ctypes.POINTER(ctypes.c_int32), i32, vp,
+                                     vp, f32, vp, vp]
+        L.sdn_mrf_cg.argtypes = [vp, vp, i32, vp, i32, ctypes.POINTER(ctypes.c_int32), i32, vp, vp,
+                                 f32, i32, vp, vp, vp]
+        L.sdn_mrf_scaled_adjoint.argtypes = [vp, vp, i32, vp, i32, ctypes.POINTER(ctypes.c_int32),
+                                             i32, vp, vp, vp, vp, vp]
+        L.sdn_tv_grad.argtypes = [vp, vp, i32, f32, f32, vp, vp, i32, vp]
         L.sdn_last_error.argtypes = []
         L.sdn_last_error.restype = ctypes.c_char_p
         for name in API:
@@ -328,6 +337,81 @@ def dcf_estimate(plan, iterations=10, out=None):
     _check(lib().sdn_dcf_estimate(plan.handle, int(iterations),
                                   _dev(out, torch.float32, "w") if plan.M else None, _stream(out)))
     return out
+
+
+def _all_coils(smaps, coil_idx):
+    return list(range(smaps.shape[0])) if coil_idx is None else coil_idx
+
+
+def mrf_normal(plan, x, smaps, V, coil_idx=None, w=None, lam=0.0, out=None):
+    """sum_b A_b^H W A_b x + lam x over the listed coils (default: all)."""
+    K = x.shape[0]
+    ci, cptr = _mrf_common(plan, K, smaps, _all_coils(smaps, coil_idx), V)
+    if out is None:
+        out = torch.empty_like(x)
+    wptr = _dev(w, torch.float32, "w") if w is not None else None
+    _check(lib().sdn_mrf_normal(plan.handle, _dev(x, torch.complex64, "x"), K,
+                                _dev(smaps, torch.complex64, "smaps"), smaps.shape[0], cptr,
+                                len(ci), _dev(V, torch.complex64, "V"), wptr, float(lam),
+                                _dev(out, torch.complex64, "out"), _stream(x)))
+    return out
+
+
+def mrf_cg(plan, y, smaps, V, x0=None, iterations=10, coil_idx=None, w=None, lam=0.0, K=None):
+    """(x, history): conjugate gradients on (sum_b A_b^H W A_b + lam) x =
+    sum_b A_b^H W y_b from x0 (default 0); history[i] = |b - N x_i|^2."""
+    if x0 is None:
+        if K is None:
+            K = V.shape[1]
+        x = torch.zeros((K,) + plan.shape, dtype=torch.complex64, device=y.device)
+    else:
+        x = x0.clone()
+    K = x.shape[0]
+    ci, cptr = _mrf_common(plan, K, smaps, _all_coils(smaps, coil_idx), V)
+    if y.shape != (len(ci), plan.M):
+        raise ValueError("y must be [B, M]")
+    hist = torch.empty(int(iterations) + 1, dtype=torch.float64, device=x.device)
+    wptr = _dev(w, torch.float32, "w") if w is not None else None
+    _check(lib().sdn_mrf_cg(plan.handle, _dev(y, torch.complex64, "y"), K,
+                            _dev(smaps, torch.complex64, "smaps"), smaps.shape[0], cptr, len(ci),
+                            _dev(V, torch.complex64, "V"), wptr, float(lam), int(iterations),
+                            _dev(x, torch.complex64, "x"), _dev(hist, torch.float64, "history"),
+                            _stream(x)))
+    return x, hist
+
+
+def mrf_scaled_adjoint(plan, y, smaps, V, coil_idx=None, w=None, out=None):
+    """(s z, s) with z = sum_b A_b^H W y_b and the least-squares scale s."""
+    K = V.shape[1]
+    ci, cptr = _mrf_common(plan, K, smaps, _all_coils(smaps, coil_idx), V)
+    if y.shape != (len(ci), plan.M):
+        raise ValueError("y must be [B, M]")
+    if out is None:
+        out = torch.empty((K,) + plan.shape, dtype=torch.complex64, device=y.device)
+    s = torch.empty(1, dtype=torch.float64, device=y.device)
+    wptr = _dev(w, torch.float32, "w") if w is not None else None
+    _check(lib().sdn_mrf_scaled_adjoint(plan.handle, _dev(y, torch.complex64, "y"), K,
+                                        _dev(smaps, torch.complex64, "smaps"), smaps.shape[0],
+                                        cptr, len(ci), _dev(V, torch.complex64, "V"), wptr,
+                                        _dev(out, torch.complex64, "x"),
+                                        _dev(s, torch.float64, "scale"), _stream(y)))
+    return out, s
+
+
+def tv_grad(plan, x, eps, lam=1.0, grad=None, accumulate=False, value=None, want_grad=True):
+    """(value, grad): lam TV(x) (float64 [1]) and lam dTV/dx (added to ``grad``
+    when accumulate) for the smoothed isotropic TV on the plan's image shape."""
+    if x.ndim != 4 or tuple(x.shape[1:]) != plan.shape:
+        raise ValueError("x must be [K, Nz, Ny, Nx]")
+    if value is None:
+        value = torch.empty(1, dtype=torch.float64, device=x.device)
+    if want_grad and grad is None:
+        grad = torch.zeros_like(x) if accumulate else torch.empty_like(x)
+    _check(lib().sdn_tv_grad(plan.handle, _dev(x, torch.complex64, "x"), x.shape[0], float(eps),
+                             float(lam), _dev(value, torch.float64, "value"),
+                             _dev(grad, torch.complex64, "grad") if want_grad else None,
+                             1 if accumulate else 0, _stream(x)))
+    return value, grad
 
 
 TUNED_KEYS = ("tile", "max_points_per_item", "spread_engine")

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libstodip_nufft.so")
-SOURCES = ["host_math.cpp", "plan.hip", "fft.hip", "gridops.hip", "api.hip", "group.hip", "tune.hip"]
+SOURCES = ["host_math.cpp", "plan.hip", "fft.hip", "gridops.hip", "api.hip", "group.hip", "tune.hip", "recon.hip"]
 
 ARCH = os.environ.get("SDN_OFFLOAD_ARCH", "gfx950")
 CXXFLAGS = [

@@ -174,6 +174,104 @@ sdn_status zero_user(float2 *a, size_t n, hipStream_t st) {
   return hip_check(hipGetLastError(), "zero fill");
 }
 
+sdn_status ensure_vec(sdn_plan_s *p, size_t elems) {
+  if (p->vecbuf_cap >= elems) return SDN_OK;
+  if (p->vecbuf) (void)hipFree(p->vecbuf);
+  p->vecbuf = nullptr;
+  p->vecbuf_cap = 0;
+  sdn_status s = hip_check(hipMalloc((void **)&p->vecbuf, elems * sizeof(float2)),
+                           "solver vectors");
+  if (s == SDN_OK) p->vecbuf_cap = elems;
+  return s;
+}
+
+sdn_status ensure_red(sdn_plan_s *p, size_t n) {
+  if (p->red_cap >= n) return SDN_OK;
+  if (p->red) (void)hipFree(p->red);
+  p->red = nullptr;
+  p->red_cap = 0;
+  sdn_status s = hip_check(hipMalloc((void **)&p->red, n * sizeof(double)), "reduction scratch");
+  if (s == SDN_OK) p->red_cap = n;
+  return s;
+}
+
+// A^H W A x over the listed coils, chunked by the workspace budget, into
+// out (accumulated across chunks; onto out's contents when accumulate);
+// loss += sum w |A x|^2.  With adjoint = false only the forward half runs
+// (loss only; out untouched).
+sdn_status normal_pass(sdn_plan_s *p, const float2 *x, int K, const float2 *smaps,
+                       const int32_t *coil_idx, int B, const float2 *V, const float *w,
+                       float2 *out, int accumulate, double *loss, bool adjoint, hipStream_t st) {
+  if (p->M == 0) {
+    if (adjoint && !accumulate) return zero_user(out, (size_t)K * image_voxels(*p), st);
+    return SDN_OK;
+  }
+  int per;
+  SDN_TRY(channels_per_pass(*p, K, B, &per, "normal operator"));
+  SDN_TRY(ensure_kbuf(p, (size_t)per * p->M));
+  for (int b0 = 0; b0 < B; b0 += per) {
+    const int bc = std::min(per, B - b0);
+    const CoilList coils = coil_list(coil_idx, b0, bc);
+    SDN_TRY(ensure_grid(p, (size_t)bc * K * fine_cells(*p)));
+    SDN_TRY(forward_grid(p, x, K, smaps, coils, bc, st));
+    InterpArgs a{};
+    a.grid = p->grid;
+    a.P = bc * K;
+    a.groups = bc;
+    a.kg = K;
+    a.V = V;
+    a.dc = 1;
+    a.rscale = 1.f;
+    a.d = nullptr;
+    a.w = w;
+    a.r_plan = p->kbuf;
+    a.loss = loss;
+    SDN_STAGE(p, SDN_STAGE_INTERP, launch_interp(*p, a, st), "interpolation + weighting");
+    if (!adjoint) continue;
+    SDN_TRY(ensure_part(p, bc, K));
+    SpreadArgs s{};
+    s.grid = p->grid;
+    s.part = p->part;
+    s.groups = bc;
+    s.K = K;
+    s.V = V;
+    s.src = p->kbuf;
+    s.src_plan_order = true;
+    SDN_STAGE(p, SDN_STAGE_SPREAD, launch_spread(*p, s, st), "spreading");
+    SDN_TRY(adjoint_grid(p, K, smaps, coils, bc, out, (accumulate || b0 > 0) ? 1 : 0, st));
+  }
+  return SDN_OK;
+}
+
+// A^H W y over the listed coils (y [B][M] in user order) into out.
+sdn_status rhs_pass(sdn_plan_s *p, const float2 *y, int K, const float2 *smaps,
+                    const int32_t *coil_idx, int B, const float2 *V, const float *w, float2 *out,
+                    hipStream_t st) {
+  if (p->M == 0) return zero_user(out, (size_t)K * image_voxels(*p), st);
+  int per;
+  SDN_TRY(channels_per_pass(*p, K, B, &per, "adjoint of the data"));
+  SDN_TRY(ensure_kbuf(p, (size_t)per * p->M));
+  for (int b0 = 0; b0 < B; b0 += per) {
+    const int bc = std::min(per, B - b0);
+    const CoilList coils = coil_list(coil_idx, b0, bc);
+    SDN_TRY(ensure_grid(p, (size_t)bc * K * fine_cells(*p)));
+    SDN_TRY(ensure_part(p, bc, K));
+    SDN_HIP(launch_weighted_plan(*p, y + (size_t)b0 * p->M, bc, w, 1.f, p->kbuf, st),
+            "weighted data");
+    SpreadArgs s{};
+    s.grid = p->grid;
+    s.part = p->part;
+    s.groups = bc;
+    s.K = K;
+    s.V = V;
+    s.src = p->kbuf;
+    s.src_plan_order = true;
+    SDN_STAGE(p, SDN_STAGE_SPREAD, launch_spread(*p, s, st), "spreading");
+    SDN_TRY(adjoint_grid(p, K, smaps, coils, bc, out, b0 > 0 ? 1 : 0, st));
+  }
+  return SDN_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -320,6 +418,8 @@ sdn_status sdn_mrf_dc_grad(sdn_plan p, const void *x, int K, const void *smaps, 
     a.groups = bc;
     a.kg = K;
     a.V = (const float2 *)V;
+    a.dc = 1;
+    a.rscale = 2.f;
     a.d = (const float2 *)d + (size_t)b0 * p->M;
     a.w = w;
     a.r_plan = p->kbuf;
@@ -440,6 +540,106 @@ sdn_status sdn_dcf_estimate(sdn_plan p, int iterations, float *w_out, void *stre
   return SDN_OK;
 }
 
+sdn_status sdn_mrf_normal(sdn_plan p, const void *x, int K, const void *smaps, int C,
+                          const int32_t *coil_idx, int B, const void *V, const float *w,
+                          float lambda, void *out, void *stream) {
+  SDN_TRY(check_plan(p, "sdn_mrf_normal"));
+  SDN_TRY(check_mrf_args(*p, "sdn_mrf_normal", x, K, smaps, C, coil_idx, B, V, x));
+  if (!out) return fail(SDN_E_INVALID, "sdn_mrf_normal: null output argument");
+  if (!(lambda >= 0.f) || lambda > 3.0e38f)
+    return fail(SDN_E_INVALID, "sdn_mrf_normal: lambda must be finite and >= 0");
+  hipStream_t st = (hipStream_t)stream;
+  const size_t n = (size_t)K * image_voxels(*p);
+  SDN_TRY(ensure_red(p, kDotBlocks + 1));
+  double *part = p->red, *loss = p->red + kDotBlocks;
+  SDN_HIP(launch_fill_zero_f64(loss, 1, st), "scratch clear");
+  SDN_TRY(normal_pass(p, (const float2 *)x, K, (const float2 *)smaps, coil_idx, B,
+                      (const float2 *)V, w, (float2 *)out, 0, loss, true, st));
+  if (lambda != 0.f)
+    SDN_HIP(launch_axpy_dot((float2 *)out, (const float2 *)x, lambda, n, part, st),
+            "Tikhonov term");
+  return SDN_OK;
+}
+
+sdn_status sdn_mrf_cg(sdn_plan p, const void *y, int K, const void *smaps, int C,
+                      const int32_t *coil_idx, int B, const void *V, const float *w, float lambda,
+                      int iterations, void *x, double *history, void *stream) {
+  SDN_TRY(check_plan(p, "sdn_mrf_cg"));
+  SDN_TRY(check_mrf_args(*p, "sdn_mrf_cg", x, K, smaps, C, coil_idx, B, V, y));
+  if (iterations < 0 || iterations > 100000)
+    return fail(SDN_E_INVALID, "sdn_mrf_cg: iterations must be in [0, 100000]");
+  if (!(lambda >= 0.f) || lambda > 3.0e38f)
+    return fail(SDN_E_INVALID, "sdn_mrf_cg: lambda must be finite and >= 0");
+  hipStream_t st = (hipStream_t)stream;
+  const size_t n = (size_t)K * image_voxels(*p);
+  SDN_TRY(ensure_vec(p, 3 * n));
+  SDN_TRY(ensure_red(p, (size_t)kDotBlocks + iterations + 3));
+  float2 *xx = (float2 *)x, *r = p->vecbuf, *q = p->vecbuf + n, *Ap = p->vecbuf + 2 * n;
+  double *part = p->red, *hist = p->red + kDotBlocks;
+  double *pAp = hist + iterations + 1, *loss = pAp + 1;
+  const float2 *S = (const float2 *)smaps, *VV = (const float2 *)V;
+  SDN_HIP(launch_fill_zero_f64(loss, 1, st), "scratch clear");
+  // r = b - (A^H W A + lambda) x0, q = r
+  SDN_TRY(rhs_pass(p, (const float2 *)y, K, S, coil_idx, B, VV, w, r, st));
+  SDN_TRY(normal_pass(p, xx, K, S, coil_idx, B, VV, w, Ap, 0, loss, true, st));
+  if (lambda != 0.f) SDN_HIP(launch_axpy_dot(Ap, xx, lambda, n, part, st), "Tikhonov term");
+  SDN_HIP(launch_cg_start(r, q, Ap, n, part, st), "cg start");
+  SDN_HIP(launch_sum(part, kDotBlocks, 1.0, hist, st), "cg residual");
+  for (int it = 0; it < iterations; ++it) {
+    SDN_TRY(normal_pass(p, q, K, S, coil_idx, B, VV, w, Ap, 0, loss, true, st));
+    SDN_HIP(launch_axpy_dot(Ap, q, lambda, n, part, st), "cg curvature");
+    SDN_HIP(launch_sum(part, kDotBlocks, 1.0, pAp, st), "cg curvature");
+    SDN_HIP(launch_cg_xr(xx, r, q, Ap, n, hist + it, pAp, part, st), "cg update");
+    SDN_HIP(launch_sum(part, kDotBlocks, 1.0, hist + it + 1, st), "cg residual");
+    SDN_HIP(launch_cg_p(q, r, n, hist + it + 1, hist + it, st), "cg direction");
+  }
+  if (history)
+    SDN_HIP(hipMemcpyAsync(history, hist, (size_t)(iterations + 1) * sizeof(double),
+                           hipMemcpyDeviceToDevice, st),
+            "cg history");
+  return SDN_OK;
+}
+
+sdn_status sdn_mrf_scaled_adjoint(sdn_plan p, const void *y, int K, const void *smaps, int C,
+                                  const int32_t *coil_idx, int B, const void *V, const float *w,
+                                  void *x_out, double *scale, void *stream) {
+  SDN_TRY(check_plan(p, "sdn_mrf_scaled_adjoint"));
+  SDN_TRY(check_mrf_args(*p, "sdn_mrf_scaled_adjoint", x_out, K, smaps, C, coil_idx, B, V, y));
+  hipStream_t st = (hipStream_t)stream;
+  const size_t n = (size_t)K * image_voxels(*p);
+  SDN_TRY(ensure_red(p, kDotBlocks + 2));
+  double *part = p->red, *num = p->red + kDotBlocks, *den = num + 1;
+  float2 *z = (float2 *)x_out;
+  const float2 *S = (const float2 *)smaps, *VV = (const float2 *)V;
+  SDN_TRY(rhs_pass(p, (const float2 *)y, K, S, coil_idx, B, VV, w, z, st));
+  SDN_HIP(launch_fill_zero_f64(den, 1, st), "scratch clear");
+  SDN_TRY(normal_pass(p, z, K, S, coil_idx, B, VV, w, nullptr, 0, den, false, st));
+  SDN_HIP(launch_dot(z, z, n, part, st), "adjoint norm");
+  SDN_HIP(launch_sum(part, kDotBlocks, 1.0, num, st), "adjoint norm");
+  SDN_HIP(launch_scale_ratio(z, n, num, den, scale, st), "adjoint scale");
+  return SDN_OK;
+}
+
+sdn_status sdn_tv_grad(sdn_plan p, const void *x, int K, float eps, float lambda, double *value,
+                       void *grad, int accumulate, void *stream) {
+  SDN_TRY(check_plan(p, "sdn_tv_grad"));
+  if (!x) return fail(SDN_E_INVALID, "sdn_tv_grad: null image argument");
+  if (!value && !grad) return fail(SDN_E_INVALID, "sdn_tv_grad: no output requested");
+  if (K < 1 || K > kMaxK) return fail(SDN_E_INVALID, "sdn_tv_grad: K must be in [1, 8]");
+  if (!(eps > 0.f) || eps > 1.0e18f)
+    return fail(SDN_E_INVALID, "sdn_tv_grad: eps must be finite and > 0");
+  if (!(lambda >= 0.f) || lambda > 3.0e38f)
+    return fail(SDN_E_INVALID, "sdn_tv_grad: lambda must be finite and >= 0");
+  hipStream_t st = (hipStream_t)stream;
+  const int nb = tv_blocks(*p, K);
+  SDN_TRY(ensure_red(p, (size_t)nb));
+  SDN_HIP(launch_tv(*p, (const float2 *)x, K, eps, lambda, (float2 *)grad, accumulate ? 1 : 0,
+                    p->red, st),
+          "total variation");
+  if (value) SDN_HIP(launch_sum(p->red, nb, (double)lambda, value, st), "total variation sum");
+  return SDN_OK;
+}
+
 sdn_status sdn_workspace_size(sdn_plan p, int B, int K, size_t *bytes) {
   SDN_TRY(check_plan(p, "sdn_workspace_size"));
   if (!bytes || B < 1 || K < 1) return fail(SDN_E_INVALID, "sdn_workspace_size: bad argument");
@@ -484,10 +684,14 @@ sdn_status sdn_release_workspace(sdn_plan p) {
   if (p->grid) (void)hipFree(p->grid);
   if (p->kbuf) (void)hipFree(p->kbuf);
   if (p->part) (void)hipFree(p->part);
+  if (p->vecbuf) (void)hipFree(p->vecbuf);
+  if (p->red) (void)hipFree(p->red);
   p->grid = nullptr;
   p->kbuf = nullptr;
   p->part = nullptr;
-  p->grid_cap = p->kbuf_cap = p->part_cap = 0;
+  p->vecbuf = nullptr;
+  p->red = nullptr;
+  p->grid_cap = p->kbuf_cap = p->part_cap = p->vecbuf_cap = p->red_cap = 0;
   return SDN_OK;
 }
 

@@ -68,6 +68,7 @@ struct InterpDev {
   const float *w;
   float2 *r_plan;
   double *loss;
+  float rscale;
 };
 
 constexpr int kThreads = 256;
@@ -180,11 +181,12 @@ __global__ void __launch_bounds__(kIThreads) k_interp(InterpDev a) {
       if (q >= wi.z) break;
       const int orig = a.pidx[wi.y + q].y;
       if constexpr (DC) {
-        const float2 dv = a.d[(size_t)grp * a.M + orig];
+        const float2 dv = a.d ? a.d[(size_t)grp * a.M + orig] : make_float2(0.f, 0.f);
         const float2 df = csub(acc[i], dv);
         const float wt = a.w ? a.w[orig] : 1.f;
         my_loss += (double)wt * ((double)df.x * df.x + (double)df.y * df.y);
-        a.r_plan[(size_t)grp * a.M + wi.y + q] = make_float2(2.f * wt * df.x, 2.f * wt * df.y);
+        const float sw = a.rscale * wt;
+        a.r_plan[(size_t)grp * a.M + wi.y + q] = make_float2(sw * df.x, sw * df.y);
       } else {
         a.y[(size_t)grp * a.M + orig] = acc[i];
       }
@@ -875,8 +877,10 @@ hipError_t launch_interp(const sdn_plan_s &p, const InterpArgs &a, hipStream_t s
   d.w = a.w;
   d.r_plan = a.r_plan;
   d.loss = a.loss;
+  d.rscale = a.rscale;
   const bool mix = a.V != nullptr;
-  const bool dc = a.d != nullptr;
+  const bool dc = a.dc != 0;
+  if (dc && (!mix || a.r_plan == nullptr || a.loss == nullptr)) return hipErrorInvalidValue;
   const size_t lds = interp_lds_bytes(p);
   if (lds > max_lds_bytes()) return hipErrorInvalidValue;
   dim3 grd((unsigned)p.nwork, (unsigned)a.groups);

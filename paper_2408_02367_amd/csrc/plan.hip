@@ -320,6 +320,11 @@ void free_plan_memory(sdn_plan_s *p) {
   p->part_cap = 0;
   if (p->grid) (void)hipFree(p->grid);
   if (p->kbuf) (void)hipFree(p->kbuf);
+  if (p->vecbuf) (void)hipFree(p->vecbuf);
+  if (p->red) (void)hipFree(p->red);
+  p->vecbuf = nullptr;
+  p->red = nullptr;
+  p->vecbuf_cap = p->red_cap = 0;
   p->rec = nullptr;
   p->pidx = nullptr;
   p->frame_user = nullptr;

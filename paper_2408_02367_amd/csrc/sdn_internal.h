@@ -109,6 +109,10 @@ struct sdn_plan_s {
   // workspace
   float2 *grid = nullptr;
   size_t grid_cap = 0;       // complex elements
+  float2 *vecbuf = nullptr;  // image-space vectors of the iterative solver
+  size_t vecbuf_cap = 0;
+  double *red = nullptr;     // reduction partials and solver scalars
+  size_t red_cap = 0;
   float2 *kbuf = nullptr;    // k-space scratch (residual / plain path)
   size_t kbuf_cap = 0;
   float2 *part = nullptr;    // partial tiles of split spreading items
@@ -136,6 +140,39 @@ namespace sdn {
 // (defined in the .hip files; all enqueue on `st`)
 hipError_t launch_fill_zero(float2 *a, size_t n, hipStream_t st);
 hipError_t launch_fill_zero_f64(double *a, size_t n, hipStream_t st);
+
+// Image-space reductions and updates (recon.hip).  Every sum of many terms
+// is two fixed-order passes (per-block partials, then one block), so
+// results do not depend on scheduling.
+constexpr int kDotBlocks = 1024;
+// part[0 .. kDotBlocks) = partial sums of Re <a, b> over n complex elements
+hipError_t launch_dot(const float2 *a, const float2 *b, size_t n, double *part, hipStream_t st);
+// *out = scale * sum(part[0 .. n))
+hipError_t launch_sum(const double *part, int n, double scale, double *out, hipStream_t st);
+// out[g][j] = scale w[orig(j)] y[g][orig(j)], plan order, for g < groups
+hipError_t launch_weighted_plan(const sdn_plan_s &p, const float2 *y, int groups, const float *w,
+                                float scale, float2 *out, hipStream_t st);
+// y += lam x, and part = partials of Re <x, y> (after the update)
+hipError_t launch_axpy_dot(float2 *y, const float2 *x, float lam, size_t n, double *part,
+                           hipStream_t st);
+// r = b - g, p = r, part = partials of |r|^2
+hipError_t launch_cg_start(float2 *r, float2 *p, const float2 *g, size_t n, double *part,
+                           hipStream_t st);
+// alpha = rs / pAp (0 when pAp <= 0): x += alpha p, r -= alpha Ap,
+// part = partials of |r|^2 (after the update)
+hipError_t launch_cg_xr(float2 *x, float2 *r, const float2 *p, const float2 *Ap, size_t n,
+                        const double *rs, const double *pAp, double *part, hipStream_t st);
+// beta = rs_new / rs (0 when rs <= 0): p = r + beta p
+hipError_t launch_cg_p(float2 *p, const float2 *r, size_t n, const double *rs_new,
+                       const double *rs, hipStream_t st);
+// s = num / den (0 when den <= 0): x *= s, *s_out = s (when non-null)
+hipError_t launch_scale_ratio(float2 *x, size_t n, const double *num, const double *den,
+                              double *s_out, hipStream_t st);
+// Smoothed isotropic TV of x [K][Nz][Ny][Nx]: grad (+)= lam dTV/dx when grad
+// is non-null; part[0 .. tv_blocks) = partial sums of the per-voxel terms
+int tv_blocks(const sdn_plan_s &p, int K);
+hipError_t launch_tv(const sdn_plan_s &p, const float2 *x, int K, float eps, float lam,
+                     float2 *grad, int accumulate, double *part, hipStream_t st);
 // Density compensation: one Pipe-Menon update (or w = 1 when first) and
 // the real parts of complex-stored weights.
 hipError_t launch_dcf_step(float2 *w, const float2 *cw, int64_t M, bool first, hipStream_t st);
@@ -164,7 +201,10 @@ struct InterpArgs {
   int kg;         // channels per group
   const float2 *V;  // [T][K] or null (no mix: kg = 1)
   float2 *y;        // [groups][M] user order (may be null in DC mode)
-  // DC epilogue: r = 2 w (y - d) in plan order, loss += w |y - d|^2
+  // DC epilogue (dc != 0): r = rscale w (y - d) in plan order and
+  // loss += w |y - d|^2, with d = 0 where d is null
+  int dc;
+  float rscale;
   const float2 *d;  // [groups][M] user order, or null
   const float *w;   // [M] user order, or null
   float2 *r_plan;   // [groups][M] plan order

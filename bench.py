@@ -23,7 +23,14 @@ import time
 
 import numpy as np
 
-WORKLOAD = "c4"
+# workload name -> description for the JSON line
+WORKLOADS = {
+    "c4": "160^3 x K=5 subspace image, 4-of-32 coil minibatch, T=1000 frames x 8 spiral "
+          "interleaves x 1200 samples (M=9.6M), KB W=6, sigma=2 (320^3 grid): batched DC gradient",
+    "paper": "paper-shaped step: 200^3 x K=5 subspace image, 1-of-8 coil minibatch (one coil "
+             "per stochastic step), T=880 frames x 28 spiral arms x 876 samples (M=21.59M), "
+             "KB W=6, sigma=2 (400^3 grid): DC gradient",
+}
 
 
 def _args():
@@ -37,6 +44,9 @@ def _args():
                     help="points of the CPU oracle sample")
     ap.add_argument("--eager", action="store_true",
                     help="time eager calls instead of replays of the captured step")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="c4",
+                    help="c4 (the default, the headline configuration) or the paper-shaped step")
+    ap.add_argument("--spread-engine", choices=["auto", "gather", "matrix"], default="auto")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -79,10 +89,13 @@ TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profile
                             "hbm_traffic_c4.txt")
 
 
-def measured_traffic(stage):
+def measured_traffic(stage, workload="c4"):
     """HBM bytes per launch of a stage from the committed FETCH_SIZE / WRITE_SIZE
-    summary, or None when there is none or the kernel source has changed since."""
+    summary, or None when there is none, it covers another workload, or the
+    kernel source has changed since."""
     import hashlib
+    if workload != "c4":
+        return None
     src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2408_02367_amd", "csrc",
                        _SOURCES.get(stage, ""))
     if not os.path.isfile(TRAFFIC_FILE) or not os.path.isfile(src):
@@ -118,11 +131,13 @@ def cpu_baseline(w, x, smaps, sample):
     grid.crop_deapodise(grid.ifft(H))
     t4 = time.perf_counter()
     t_grid = (t1 - t0) + (t4 - t3)
+    shape_s = "x".join(str(n) for n in w["shape"])
+    fine_s = "x".join(str(n) for n in grid.nf)
     t_pts = (t3 - t1) * (M / len(sel))
     return {"value": M / (t_grid + t_pts), "unit": "pts*ch/s", "cores": _WORKERS,
             "kind": "oracle",
-            "sample": f"one (coil, channel) fwd+adj of the 160^3 workload: deapodise/FFT/IFFT/"
-                      f"crop on the full 320^3 grid ({t_grid:.2f} s), interp+spread on "
+            "sample": f"one (coil, channel) fwd+adj of the {shape_s} workload: deapodise/FFT/"
+                      f"IFFT/crop on the full {fine_s} grid ({t_grid:.2f} s), interp+spread on "
                       f"{len(sel)} of {M} points ({t3 - t1:.2f} s) scaled to all points",
             "seconds": t4 - t0}
 
@@ -145,7 +160,7 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     _log("drawing the synthetic workload")
-    w = wl.make(WORKLOAD)
+    w = wl.make(a.workload)
     shape, K, B = w["shape"], w["K"], w["B"]
     M = w["traj"].shape[0]
     x_true = w["x"]
@@ -156,7 +171,8 @@ def main():
 
     _log("building the plan")
     plan = sdn.Plan(torch.from_numpy(w["traj"]).to(dev), shape,
-                    frame_of_point=torch.from_numpy(w["frame"]).to(dev), T=w["T"])
+                    frame_of_point=torch.from_numpy(w["frame"]).to(dev), T=w["T"],
+                    spread_engine=a.spread_engine)
     info = plan.info()
     smaps = torch.from_numpy(w["smaps"]).to(dev)
     V = torch.from_numpy(w["V"]).to(dev)
@@ -295,7 +311,7 @@ def main():
         roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0,
                     "unit": "GB/s", "frac": round(achieved / 8000.0, 4),
                     "algo_bytes_per_launch": sb[dom]}
-    roofline["traffic"] = measured_traffic(dom)
+    roofline["traffic"] = measured_traffic(dom, a.workload)
     roofline["avg_launch_ms"] = round(dom_avg_s * 1e3, 4)
 
     out = {
@@ -314,9 +330,8 @@ def main():
         "vs_baseline": None,
         "dtype": "fp32",
         "data": "synthetic",
-        "config": {"workload": "160^3 x K=5 subspace image, 4-of-32 coil minibatch, "
-                               "T=1000 frames x 8 spiral interleaves x 1200 samples "
-                               "(M=9.6M), KB W=6, sigma=2 (320^3 grid): batched DC gradient",
+        "config": {"workload": WORKLOADS[a.workload], "name": a.workload,
+                   "spread_engine": info["spread_engine"],
                    "shape": list(shape), "K": K, "B": B, "C": w["C"], "M": M, "T": w["T"],
                    "W": info["W"], "sigma": info["sigma"]},
         "plain_ms_per_step": round(plain_ms, 3) if plain_ms else None,

@@ -68,8 +68,10 @@ typedef struct {
                               0 = library choice (2048)                              */
   size_t workspace_budget; /* bytes of fine-grid workspace; 0 = unlimited.  Calls
                               whose coil minibatch does not fit run coil-chunked.   */
-  int spread_engine;       /* type-1 spreading kernel: SDN_SPREAD_AUTO (default),
-                              SDN_SPREAD_GATHER (vector ALU gather into registers) or
+  int spread_engine;       /* type-1 spreading kernel: SDN_SPREAD_AUTO (default:
+                              the matrix cores when a call spreads >= 2 coils of
+                              >= 2 channels, else the gather), SDN_SPREAD_GATHER
+                              (vector ALU gather into registers) or
                               SDN_SPREAD_MATRIX (matrix cores, split fp16 products
                               with FP32 accumulation; needs every fine axis >= 16
                               and >= 2 channels per call, else the gather runs)     */
@@ -92,8 +94,8 @@ typedef struct {
   int64_t max_bin;         /* points in the most populated tile                      */
   int ncoef;               /* coefficients per piece of the kernel polynomial        */
   int64_t nvisit;          /* (point, tile) pairs of the spreading lists             */
-  int spread_engine;       /* engine a call with >= 2 channels per coil uses:
-                              SDN_SPREAD_GATHER or SDN_SPREAD_MATRIX                 */
+  int spread_engine;       /* engine a call with >= 2 coils of >= 2 channels
+                              uses: SDN_SPREAD_GATHER or SDN_SPREAD_MATRIX           */
 } sdn_plan_info;
 
 /* Library defaults: W = 6, sigma = 2, automatic tiles, no budget. */

@@ -388,7 +388,9 @@ __global__ void k_combine(PostArgs a) {
 
 bool fft_len_ct(int L) {
   switch (L) {
-    case 64: case 128: case 192: case 256: case 320: case 384: case 448: return true;
+    case 64: case 96: case 128: case 160: case 192: case 224: case 256: case 288: case 320:
+    case 384: case 400: case 448:
+      return true;
     default: return false;
   }
 }
@@ -425,8 +427,8 @@ hipError_t launch_pre_fftx(const sdn_plan_s &p, const float2 *x, int K, const fl
 #define SDN_PRE_CT(LEN) \
   case LEN: hipLaunchKernelGGL(k_pre_fftx_ct<LEN>, grd, dim3(kFftThreads), 0, st, a, inv_nx, inv_p); break;
     switch (L) {
-      SDN_PRE_CT(64) SDN_PRE_CT(128) SDN_PRE_CT(192) SDN_PRE_CT(256) SDN_PRE_CT(320)
-      SDN_PRE_CT(384) SDN_PRE_CT(448)
+      SDN_PRE_CT(64) SDN_PRE_CT(96) SDN_PRE_CT(128) SDN_PRE_CT(160) SDN_PRE_CT(192) SDN_PRE_CT(224) SDN_PRE_CT(256)
+      SDN_PRE_CT(288) SDN_PRE_CT(320) SDN_PRE_CT(384) SDN_PRE_CT(400) SDN_PRE_CT(448)
     }
 #undef SDN_PRE_CT
     return hipGetLastError();
@@ -472,8 +474,8 @@ hipError_t launch_post_ifftx(const sdn_plan_s &p, const float2 *grid, int K,
 #define SDN_CROP_CT(LEN) \
   case LEN: hipLaunchKernelGGL(k_ifftx_crop_ct<LEN>, grd, dim3(kFftThreads), 0, st, c, inv_nx); break;
     switch (L) {
-      SDN_CROP_CT(64) SDN_CROP_CT(128) SDN_CROP_CT(192) SDN_CROP_CT(256) SDN_CROP_CT(320)
-      SDN_CROP_CT(384) SDN_CROP_CT(448)
+      SDN_CROP_CT(64) SDN_CROP_CT(96) SDN_CROP_CT(128) SDN_CROP_CT(160) SDN_CROP_CT(192) SDN_CROP_CT(224) SDN_CROP_CT(256)
+      SDN_CROP_CT(288) SDN_CROP_CT(320) SDN_CROP_CT(384) SDN_CROP_CT(400) SDN_CROP_CT(448)
     }
 #undef SDN_CROP_CT
     hipError_t e = hipGetLastError();
@@ -553,11 +555,16 @@ hipError_t launch_fft_axis(const sdn_plan_s &p, float2 *grid, int P, int axis, b
     return hipGetLastError();
     switch (a.L) {
       SDN_AXIS_CT(64)
+      SDN_AXIS_CT(96)
       SDN_AXIS_CT(128)
+      SDN_AXIS_CT(160)
       SDN_AXIS_CT(192)
+      SDN_AXIS_CT(224)
       SDN_AXIS_CT(256)
+      SDN_AXIS_CT(288)
       SDN_AXIS_CT(320)
       SDN_AXIS_CT(384)
+      SDN_AXIS_CT(400)
       SDN_AXIS_CT(448)
       default: break;
     }

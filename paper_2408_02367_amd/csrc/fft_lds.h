@@ -232,6 +232,11 @@ SDN_RADIX_SEQ(256, 4, 8, 8)
 SDN_RADIX_SEQ(320, 8, 8, 5)
 SDN_RADIX_SEQ(384, 6, 8, 8)
 SDN_RADIX_SEQ(448, 8, 8, 7)
+SDN_RADIX_SEQ(96, 4, 8, 3)
+SDN_RADIX_SEQ(160, 4, 8, 5)
+SDN_RADIX_SEQ(224, 4, 8, 7)
+SDN_RADIX_SEQ(288, 4, 8, 3, 3)
+SDN_RADIX_SEQ(400, 4, 4, 5, 5)
 #undef SDN_RADIX_SEQ
 
 // Transform all C columns; `tw` = exp(-2 pi i m / L) (inverse uses conj).

@@ -919,8 +919,11 @@ hipError_t spread_mma(const SpreadDev &d, int K, dim3 grd, const unsigned *absma
 
 // The matrix-core spreading needs every fine axis >= 16 cells (no support
 // touches both ends of a block) and at least two channels per group.
-bool spread_engine_for(const sdn_plan_s &p, int K) {
+bool spread_engine_for(const sdn_plan_s &p, int K, int groups) {
   if (p.spread_engine == SDN_SPREAD_GATHER) return false;
+  // automatic choice: the matrix cores pay once several coils share the
+  // point data of a block; a single coil group keeps the gather
+  if (p.spread_engine == SDN_SPREAD_AUTO && groups < 2) return false;
   return K >= 2 && p.ax[0].nf >= 16 && p.ax[1].nf >= 16 && p.ax[2].nf >= 16 &&
          p.absmax != nullptr && (p.vinfo != nullptr || p.nvisit == 0);
 }
@@ -964,7 +967,7 @@ hipError_t launch_spread(const sdn_plan_s &p, const SpreadArgs &a, hipStream_t s
   const bool mix = a.V != nullptr;
   dim3 grd((unsigned)p.nsitems, (unsigned)a.groups);
   hipError_t e;
-  if (spread_engine_for(p, a.K)) {
+  if (spread_engine_for(p, a.K, a.groups)) {
     // value scale: the largest input component (and of V when mixing)
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, p.absmax, 2);
     const size_t nsrc = (size_t)a.groups * (mix ? 1 : a.K) * p.M * 2;

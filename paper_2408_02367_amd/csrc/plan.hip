@@ -681,7 +681,7 @@ sdn_status sdn_plan_get_info(sdn_plan p, sdn_plan_info *info) {
   info->nwork = p->nwork;
   info->max_bin = p->max_bin;
   info->nvisit = p->nvisit;
-  info->spread_engine = spread_engine_for(*p, 2) ? SDN_SPREAD_MATRIX : SDN_SPREAD_GATHER;
+  info->spread_engine = spread_engine_for(*p, 2, 2) ? SDN_SPREAD_MATRIX : SDN_SPREAD_GATHER;
   info->ncoef = p->ncoef;
   return SDN_OK;
 }

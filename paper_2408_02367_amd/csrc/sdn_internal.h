@@ -228,8 +228,9 @@ struct SpreadArgs {
   bool src_plan_order;
 };
 hipError_t launch_spread(const sdn_plan_s &p, const SpreadArgs &a, hipStream_t st);
-// True when a spreading call with K channels per coil runs on the matrix cores.
-bool spread_engine_for(const sdn_plan_s &p, int K);
+// True when a spreading call with K channels per group and `groups` groups
+// (coils) runs on the matrix cores.
+bool spread_engine_for(const sdn_plan_s &p, int K, int groups);
 size_t spread_part_elems(const sdn_plan_s &p, int groups, int K);
 
 // Plain-path subspace mix kernels (user order).

@@ -196,8 +196,12 @@ CONFIGS = {
     "c4": dict(shape=(160, 160, 160), K=5, C=32, B=4, T=1000, L=8, S=1200),
     # large DC step: 224^3 x K=6, 8-of-48 coils, M = 20.16M
     "c5": dict(shape=(224, 224, 224), K=6, C=48, B=8, T=1200, L=12, S=1400),
+    # the paper's own iteration shape (Sec. 3: 200^3 volume, 8 coils, 880
+    # frames, 28 spiral arms per frame at R = 2, 876 samples per arm; one
+    # coil per stochastic step as in Alg. 1), K = 5 channels: M = 21.59M
+    "paper": dict(shape=(200, 200, 200), K=5, C=8, B=1, T=880, L=28, S=876),
 }
-SEEDS = {"c1": 1, "c2": 2, "c3": 3, "c3r128": 31, "c3r192": 32, "c4": 4, "c5": 5}
+SEEDS = {"c1": 1, "c2": 2, "c3": 3, "c3r128": 31, "c3r192": 32, "c4": 4, "c5": 5, "paper": 6}
 
 
 def make(name, with_images=True, minibatch_maps=False):

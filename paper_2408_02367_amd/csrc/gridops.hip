@@ -55,7 +55,9 @@ TileGeom tile_geom(const sdn_plan_s &p) {
 struct InterpDev {
   const float4 *rec;
   const int2 *pidx;
-  const float *wts;    // per point: W weights for x, y, z
+  const float *wts_t;  // transposed weights [3W][M], then packed first nodes [M]
+  unsigned row_bytes;  // 4 M
+  unsigned rec_bytes;  // 4 M (3W + 1), when below 4 GiB
   const int4 *work;
   int M;
   TileGeom g;
@@ -81,9 +83,12 @@ constexpr int kIThreads = 512;                // interpolation workgroup
 // that every 16 consecutive points start at tile cells of distinct residues
 // mod 16; each 16-lane group's 8-byte LDS reads then hit distinct banks at
 // every one of the W^3 offsets.
-template <int W, bool MIX, bool DC>
+template <int W, bool MIX, bool DC, bool BUF>
 __global__ void __launch_bounds__(kIThreads) k_interp(InterpDev a) {
   extern __shared__ float2 tile[];
+  // raw buffer over the transposed records (word 3: the gfx9 raw-buffer format)
+  const __amdgpu_buffer_rsrc_t wrsrc = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float *>(a.wts_t), 0, (int)a.rec_bytes, 0x00020000);
   const TileGeom &g = a.g;
   const int4 wi = a.work[blockIdx.x];
   const int grp = blockIdx.y;
@@ -117,18 +122,26 @@ __global__ void __launch_bounds__(kIThreads) k_interp(InterpDev a) {
       const int q = tid + i * kIThreads;
       if (q >= wi.z) break;
       const int2 id = a.pidx[wi.y + q];
+      // transposed records: a wave's consecutive points are contiguous.
+      // Buffer loads share one lane offset and take the row offset from a
+      // scalar register (records under 4 GiB); else plain global loads.
+      const unsigned jb = (unsigned)(wi.y + q) * 4u;
+      auto row = [&](int c) -> float {
+        if constexpr (BUF)
+          return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
+              wrsrc, (int)jb, (int)((unsigned)c * a.row_bytes), 0));
+        else
+          return a.wts_t[(size_t)c * a.M + wi.y + q];
+      };
       int lx, ly, lz;
-      unpack_l0(a.rec[wi.y + q].w, lx, ly, lz);
+      unpack_l0(row(3 * W), lx, ly, lz);
       lx -= ox; ly -= oy; lz -= oz;
-      static_assert((3 * W) % 2 == 0, "weights are read as float2");
-      const float2 *wp = reinterpret_cast<const float2 *>(a.wts + (size_t)(wi.y + q) * 3 * W);
       float wx[W], wy[W], wz[W];
 #pragma unroll
-      for (int c = 0; c < 3 * W / 2; ++c) {
-        const float2 t = wp[c];
-        const int e0 = 2 * c, e1 = 2 * c + 1;
-        (e0 < W ? wx[e0] : e0 < 2 * W ? wy[e0 - W] : wz[e0 - 2 * W]) = t.x;
-        (e1 < W ? wx[e1] : e1 < 2 * W ? wy[e1 - W] : wz[e1 - 2 * W]) = t.y;
+      for (int c = 0; c < W; ++c) {
+        wx[c] = row(c);
+        wy[c] = row(W + c);
+        wz[c] = row(2 * W + c);
       }
       // half a kernel plane at a time: its cells are read into registers
       // first, so those reads are in flight together
@@ -811,20 +824,27 @@ namespace {
 template <typename F>
 hipError_t allow_lds_fwd(F *kernel, size_t bytes);
 
-template <int W, bool MIX, bool DC>
+template <int W, bool MIX, bool DC, bool BUF>
 hipError_t interp_one(const InterpDev &d, dim3 grd, size_t lds, hipStream_t st) {
-  hipError_t e = allow_lds_fwd(k_interp<W, MIX, DC>, lds);
+  hipError_t e = allow_lds_fwd(k_interp<W, MIX, DC, BUF>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_interp<W, MIX, DC>), grd, dim3(kIThreads), lds, st, d);
+  hipLaunchKernelGGL((k_interp<W, MIX, DC, BUF>), grd, dim3(kIThreads), lds, st, d);
   return hipGetLastError();
+}
+
+template <int W, bool BUF>
+hipError_t interp_launch_b(const InterpDev &d, bool mix, bool dc, dim3 grd, size_t lds,
+                           hipStream_t st) {
+  if (mix && dc) return interp_one<W, true, true, BUF>(d, grd, lds, st);
+  if (mix) return interp_one<W, true, false, BUF>(d, grd, lds, st);
+  return interp_one<W, false, false, BUF>(d, grd, lds, st);
 }
 
 template <int W>
 hipError_t interp_launch(const InterpDev &d, bool mix, bool dc, dim3 grd, size_t lds,
                          hipStream_t st) {
-  if (mix && dc) return interp_one<W, true, true>(d, grd, lds, st);
-  if (mix) return interp_one<W, true, false>(d, grd, lds, st);
-  return interp_one<W, false, false>(d, grd, lds, st);
+  return d.rec_bytes ? interp_launch_b<W, true>(d, mix, dc, grd, lds, st)
+                     : interp_launch_b<W, false>(d, mix, dc, grd, lds, st);
 }
 
 }  // namespace
@@ -863,7 +883,11 @@ hipError_t launch_interp(const sdn_plan_s &p, const InterpArgs &a, hipStream_t s
   InterpDev d;
   d.rec = p.rec;
   d.pidx = p.pidx;
-  d.wts = p.wts;
+  d.wts_t = p.wts_t;
+  const uint64_t rec_bytes = (uint64_t)p.M * (3 * p.W + 1) * 4;
+  const bool buf = rec_bytes < (1ull << 31);
+  d.row_bytes = (unsigned)(p.M * 4);
+  d.rec_bytes = buf ? (unsigned)rec_bytes : 0u;
   d.work = p.work;
   d.M = (int)p.M;
   d.g = tile_geom(p);

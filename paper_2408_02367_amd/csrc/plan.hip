@@ -266,23 +266,27 @@ sdn_status exclusive_sum(const int *in, int *out, int n, hipStream_t st) {
 
 // Kernel weights of every point (plan order), evaluated once per plan with
 // the same polynomial the grid kernels use.
+// Both layouts: per point (spreading reads one scattered point per lane) and
+// transposed (interpolation reads consecutive points per lane).
 template <int W, int NC>
 __global__ void k_weights(const float4 *__restrict__ rec, int M, KerCoef kc,
-                          float *__restrict__ wts) {
+                          float *__restrict__ wts, float *__restrict__ wts_t) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= M) return;
   const float4 r = rec[j];
   float w[W];
   float *o = wts + (size_t)j * 3 * W;
-  axis_weights<W, NC>(r.x, kc, w);
+  const float tc[3] = {r.x, r.y, r.z};
 #pragma unroll
-  for (int i = 0; i < W; ++i) o[i] = w[i];
-  axis_weights<W, NC>(r.y, kc, w);
+  for (int d = 0; d < 3; ++d) {
+    axis_weights<W, NC>(tc[d], kc, w);
 #pragma unroll
-  for (int i = 0; i < W; ++i) o[W + i] = w[i];
-  axis_weights<W, NC>(r.z, kc, w);
-#pragma unroll
-  for (int i = 0; i < W; ++i) o[2 * W + i] = w[i];
+    for (int i = 0; i < W; ++i) {
+      o[d * W + i] = w[i];
+      wts_t[(size_t)(d * W + i) * M + j] = w[i];
+    }
+  }
+  wts_t[(size_t)3 * W * M + j] = r.w;
 }
 
 void free_plan_memory(sdn_plan_s *p) {
@@ -309,7 +313,9 @@ void free_plan_memory(sdn_plan_s *p) {
   if (p->vinfo) (void)hipFree(p->vinfo);
   p->vinfo = nullptr;
   if (p->wts) (void)hipFree(p->wts);
+  if (p->wts_t) (void)hipFree(p->wts_t);
   p->wts = nullptr;
+  p->wts_t = nullptr;
   if (p->sitems) (void)hipFree(p->sitems);
   if (p->splits) (void)hipFree(p->splits);
   if (p->part) (void)hipFree(p->part);
@@ -547,13 +553,17 @@ sdn_status sdn_plan_create(sdn_plan *out, const int64_t shape[3], const float *t
     }
     // per-point kernel weights
     if (s == SDN_OK) s = dalloc(&p->wts, (size_t)m * 3 * p->W, "plan weights");
+    if (s == SDN_OK) s = dalloc(&p->wts_t, (size_t)m * (3 * p->W + 1), "plan weights");
     if (s == SDN_OK) {
       if (p->W == 4)
-        hipLaunchKernelGGL((k_weights<4, 8>), grd, dim3(256), 0, st, p->rec, m, p->coef, p->wts);
+        hipLaunchKernelGGL((k_weights<4, 8>), grd, dim3(256), 0, st, p->rec, m, p->coef, p->wts,
+                           p->wts_t);
       else if (p->W == 8)
-        hipLaunchKernelGGL((k_weights<8, 12>), grd, dim3(256), 0, st, p->rec, m, p->coef, p->wts);
+        hipLaunchKernelGGL((k_weights<8, 12>), grd, dim3(256), 0, st, p->rec, m, p->coef, p->wts,
+                           p->wts_t);
       else
-        hipLaunchKernelGGL((k_weights<6, 10>), grd, dim3(256), 0, st, p->rec, m, p->coef, p->wts);
+        hipLaunchKernelGGL((k_weights<6, 10>), grd, dim3(256), 0, st, p->rec, m, p->coef, p->wts,
+                           p->wts_t);
       s = hip_check(hipGetLastError(), "plan weights kernel");
     }
     // spreading lists: entries per block and per point, scan, (block,

@@ -96,6 +96,8 @@ struct sdn_plan_s {
   int32_t *frame_user = nullptr;  // frame per point, user order
   int4 *work = nullptr;      // interpolation items: (tile, start, count, 0)
   float *wts = nullptr;      // per point (plan order): W weights per axis, x then y then z
+  float *wts_t = nullptr;    // the same transposed, [3W][M], then [M] packed first-node bits:
+                             // consecutive points' values are contiguous (interpolation)
   int *vlist = nullptr;      // spreading lists: plan indices of the points whose support
                              // touches a spreading block, grouped by block
   int2 *vinfo = nullptr;     // per list entry, matrix-core engine only: (frame, original

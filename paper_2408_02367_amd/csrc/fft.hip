@@ -277,25 +277,42 @@ k_pre_fftx_ct(PreArgs a, float inv_nx, float inv_p) {
   const int line0 = blockIdx.x * C;
   const int nlines = g.Nz * g.Ny * a.P;
   const size_t nvox = (size_t)g.Nz * g.Ny * g.Nx;
-  for (int m = tid; m < L; m += kFftThreads) tw[m] = a.tw[m];
-  for (int e = tid; e < (L - g.Nx) * C; e += kFftThreads) {
-    const int c = e % C, r = e / C;
-    lds[((g.Nx - g.hx) + r) * S + c] = make_float2(0.f, 0.f);
-  }
-  for (int e = tid; e < C * g.Nx; e += kFftThreads) {
-    const int c = qdiv(e, inv_nx);
-    const int xq = e - c * g.Nx;
-    const int line = line0 + c;
-    float2 v = make_float2(0.f, 0.f);
+  // per-line geometry, once per workgroup: image and coil rows, the y/z
+  // deapodisation factor and the output line (none: line past the end)
+  __shared__ const float2 *xrow[C], *srow[C];
+  __shared__ float scyz[C];
+  __shared__ float2 *orow[C];
+  if (tid < C) {
+    const int line = line0 + tid;
+    xrow[tid] = srow[tid] = nullptr;
+    orow[tid] = nullptr;
+    scyz[tid] = 0.f;
     if (line < nlines) {
       const int zy = qdiv(line, inv_p);
       const int p = line - zy * a.P;
       const int z = zy / g.Ny, y = zy - z * g.Ny;
       const int b = p / a.K, k = p - b * a.K;
-      const size_t vox = (size_t)zy * g.Nx + xq;
-      v = a.x[(size_t)k * nvox + vox];
-      if (a.smaps) v = cmul(a.smaps[(size_t)a.coils.idx[b] * nvox + vox], v);
-      const float sc = a.dx[xq] * a.dy[y] * a.dz[z];
+      xrow[tid] = a.x + (size_t)k * nvox + (size_t)zy * g.Nx;
+      srow[tid] = a.smaps ? a.smaps + (size_t)a.coils.idx[b] * nvox + (size_t)zy * g.Nx : nullptr;
+      scyz[tid] = a.dy[y] * a.dz[z];
+      const size_t zf = fine_pos(z, g.hz, g.nfz), yf = fine_pos(y, g.hy, g.nfy);
+      orow[tid] = a.grid + (((size_t)p * g.nfz + zf) * g.nfy + yf) * L;
+    }
+  }
+  for (int m = tid; m < L; m += kFftThreads) tw[m] = a.tw[m];
+  for (int e = tid; e < (L - g.Nx) * C; e += kFftThreads) {
+    const int c = e % C, r = e / C;
+    lds[((g.Nx - g.hx) + r) * S + c] = make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  for (int e = tid; e < C * g.Nx; e += kFftThreads) {
+    const int c = qdiv(e, inv_nx);
+    const int xq = e - c * g.Nx;
+    float2 v = make_float2(0.f, 0.f);
+    if (xrow[c]) {
+      v = xrow[c][xq];
+      if (srow[c]) v = cmul(srow[c][xq], v);
+      const float sc = a.dx[xq] * scyz[c];
       v.x *= sc;
       v.y *= sc;
     }
@@ -305,13 +322,7 @@ k_pre_fftx_ct(PreArgs a, float inv_nx, float inv_p) {
   RadixSeq<L>::template run<false, C, S, kFftThreads>(lds, tw);
   for (int e = tid; e < C * L; e += kFftThreads) {
     const int l = e % L, c = e / L;
-    const int line = line0 + c;
-    if (line >= nlines) continue;
-    const int zy = qdiv(line, inv_p);
-    const int p = line - zy * a.P;
-    const int z = zy / g.Ny, y = zy - z * g.Ny;
-    const size_t zf = fine_pos(z, g.hz, g.nfz), yf = fine_pos(y, g.hy, g.nfy);
-    a.grid[(((size_t)p * g.nfz + zf) * g.nfy + yf) * L + l] = lds[l * S + c];
+    if (orow[c]) orow[c][l] = lds[l * S + c];
   }
 }
 
@@ -335,55 +346,59 @@ k_ifftx_crop_ct(CropArgs a, float inv_nx) {
   const int tid = threadIdx.x;
   const int line0 = blockIdx.x * C;
   const int nlines = a.P * g.Nz * g.Ny;
+  // the grid line of every column, once per workgroup (none: past the end)
+  __shared__ float2 *row[C];
+  if (tid < C) {
+    const int line = line0 + tid;
+    row[tid] = nullptr;
+    if (line < nlines) {
+      const int y = line % g.Ny, pz = line / g.Ny;
+      const int z = pz % g.Nz, p = pz / g.Nz;
+      const size_t zf = fine_pos(z, g.hz, g.nfz), yf = fine_pos(y, g.hy, g.nfy);
+      row[tid] = a.grid + (((size_t)p * g.nfz + zf) * g.nfy + yf) * L;
+    }
+  }
   for (int m = tid; m < L; m += kFftThreads) tw[m] = a.tw[m];
-  auto line_base = [&](int line) -> size_t {
-    const int y = line % g.Ny, pz = line / g.Ny;
-    const int z = pz % g.Nz, p = pz / g.Nz;
-    const size_t zf = fine_pos(z, g.hz, g.nfz), yf = fine_pos(y, g.hy, g.nfy);
-    return (((size_t)p * g.nfz + zf) * g.nfy + yf) * L;
-  };
+  __syncthreads();
   for (int e = tid; e < C * L; e += kFftThreads) {
     const int l = e % L, c = e / L;
-    const int line = line0 + c;
-    lds[l * S + c] = line < nlines ? a.grid[line_base(line) + l] : make_float2(0.f, 0.f);
+    lds[l * S + c] = row[c] ? row[c][l] : make_float2(0.f, 0.f);
   }
   __syncthreads();
   RadixSeq<L>::template run<true, C, S, kFftThreads>(lds, tw);
   for (int e = tid; e < C * g.Nx; e += kFftThreads) {
     const int c = qdiv(e, inv_nx);
     const int xq = e - c * g.Nx;
-    const int line = line0 + c;
-    if (line >= nlines) continue;
-    a.grid[line_base(line) + xq] = lds[fine_pos(xq, g.hx, L) * S + c];
+    if (row[c]) row[c][xq] = lds[fine_pos(xq, g.hx, L) * S + c];
   }
 }
 
 // xout[k] (+)= sum_b conj(S_b) h_{b,k} / deapodisation, h the cropped lines.
-__global__ void k_combine(PostArgs a) {
+// Grid (ceil(Nx / 64), ceil(Ny / 4), Nz K): the row (k, z, y) comes from the
+// block and thread indices, no per-voxel division.
+__global__ void __launch_bounds__(256) k_combine(PostArgs a) {
   const LineGeom &g = a.g;
+  const int xq = blockIdx.x * 64 + threadIdx.x;
+  const int y = blockIdx.y * 4 + threadIdx.y;
+  if (xq >= g.Nx || y >= g.Ny) return;
+  const int k = blockIdx.z / g.Nz, z = blockIdx.z - k * g.Nz;
   const size_t nvox = (size_t)g.Nz * g.Ny * g.Nx;
-  const size_t n = (size_t)a.K * nvox;
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (size_t)gridDim.x * blockDim.x) {
-    const int k = (int)(i / nvox);
-    const size_t vox = i - (size_t)k * nvox;
-    const int xq = (int)(vox % g.Nx);
-    const size_t zy = vox / g.Nx;
-    const int y = (int)(zy % g.Ny), z = (int)(zy / g.Ny);
-    const size_t zf = fine_pos(z, g.hz, g.nfz), yf = fine_pos(y, g.hy, g.nfy);
-    float2 acc = make_float2(0.f, 0.f);
-    for (int b = 0; b < a.B; ++b) {
-      const int p = b * a.K + k;
-      const float2 h = a.grid[(((size_t)p * g.nfz + zf) * g.nfy + yf) * g.nfx + xq];
-      if (a.smaps) acc = cadd(acc, cmulc(h, a.smaps[(size_t)a.coils.idx[b] * nvox + vox]));
-      else acc = cadd(acc, h);
-    }
-    const float sc = a.dx[xq] * a.dy[y] * a.dz[z];
-    acc.x *= sc;
-    acc.y *= sc;
-    if (a.accumulate) acc = cadd(acc, a.xout[i]);
-    a.xout[i] = acc;
+  const size_t vox = ((size_t)z * g.Ny + y) * g.Nx + xq;
+  const size_t zf = fine_pos(z, g.hz, g.nfz), yf = fine_pos(y, g.hy, g.nfy);
+  const size_t G = (size_t)g.nfz * g.nfy * g.nfx;
+  const float2 *h = a.grid + (zf * g.nfy + yf) * g.nfx + xq;
+  float2 acc = make_float2(0.f, 0.f);
+  for (int b = 0; b < a.B; ++b) {
+    const float2 hv = h[(size_t)(b * a.K + k) * G];
+    if (a.smaps) acc = cadd(acc, cmulc(hv, a.smaps[(size_t)a.coils.idx[b] * nvox + vox]));
+    else acc = cadd(acc, hv);
   }
+  const float sc = a.dx[xq] * a.dy[y] * a.dz[z];
+  acc.x *= sc;
+  acc.y *= sc;
+  const size_t i = (size_t)k * nvox + vox;
+  if (a.accumulate) acc = cadd(acc, a.xout[i]);
+  a.xout[i] = acc;
 }
 
 bool fft_len_ct(int L) {
@@ -480,9 +495,10 @@ hipError_t launch_post_ifftx(const sdn_plan_s &p, const float2 *grid, int K,
 #undef SDN_CROP_CT
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const size_t n = (size_t)K * a.g.Nz * a.g.Ny * a.g.Nx;
-    const unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 1u << 16);
-    hipLaunchKernelGGL(k_combine, dim3(blocks), dim3(256), 0, st, a);
+    if ((int64_t)K * a.g.Nz > 65535) return hipErrorInvalidValue;
+    dim3 cg((unsigned)((a.g.Nx + 63) / 64), (unsigned)((a.g.Ny + 3) / 4),
+             (unsigned)(K * a.g.Nz));
+    hipLaunchKernelGGL(k_combine, cg, dim3(64, 4), 0, st, a);
     return hipGetLastError();
   }
   const int cap = kFftLdsElems / L - 2;

@@ -34,3 +34,22 @@ def test_specialised_lengths_match_direct(shape):
     sel = tuple(np.sort(g.choice(n, 3, replace=False)) for n in shape)
     ref1 = nudft.type1(cc.astype(np.complex128), k.astype(np.float64), shape, sel=sel)
     assert rel(img[np.ix_(*sel)], ref1) < TOL_DIRECT
+
+
+def test_plan_with_records_above_two_gib_matches_direct():
+    """29M points: the transposed per-point records exceed 2 GiB, so the
+    interpolation reads them with plain global loads instead of buffer loads."""
+    import torch
+    M, shape = 29_000_000, (24, 20, 16)
+    g = torch.Generator(device="cuda").manual_seed(21)
+    k = (torch.rand(M, 3, generator=g, device="cuda") * (2 * np.pi) - np.pi).contiguous()
+    p = sdn.Plan(k, shape)
+    assert M * (3 * 6 + 1) * 4 > 2 ** 31
+    f = cimg(shape, 22)
+    c = p.forward(c64(f[None]))[0]
+    idx = np.random.default_rng(23).choice(M, 24, replace=False)
+    kk = host(k[torch.from_numpy(idx).cuda()]).astype(np.float64)
+    ref = nudft.type2(f.astype(np.complex128), kk, chunk=24)
+    assert rel(host(c[torch.from_numpy(idx).cuda()]), ref) < TOL_DIRECT
+    del c, p
+    torch.cuda.synchronize()

@@ -373,6 +373,63 @@ k_ifftx_crop_ct(CropArgs a, float inv_nx) {
   }
 }
 
+// Inverse x pass fused with the coil combine, for B coils with B | 16: the
+// 16 columns of a workgroup are the B coils' lines of 16 / B image rows of
+// one (channel k, plane z), column c = r B + b.  After the transform the
+// workgroup forms xout[k] (+)= sum_b conj(S_b) h_b / deapodisation for its
+// rows directly from LDS, so the cropped lines never go back to HBM.
+// Grid: (ceil(Ny / R), Nz, K) with R = 16 / B rows per workgroup.
+template <int L>
+__global__ void __launch_bounds__(kFftThreads)
+k_ifftx_post_ct(PostArgs a) {
+  constexpr int C = 16, S = 17;
+  __shared__ float2 lds[L * S];
+  __shared__ float2 tw[L];
+  __shared__ const float2 *col[C];
+  const LineGeom &g = a.g;
+  const int tid = threadIdx.x;
+  const int B = a.B, R = C / B;
+  const int y0 = blockIdx.x * R, z = blockIdx.y, k = blockIdx.z;
+  const size_t zf = fine_pos(z, g.hz, g.nfz);
+  if (tid < C) {
+    const int r = tid / B, b = tid - r * B;
+    const int y = y0 + r;
+    col[tid] = nullptr;
+    if (y < g.Ny) {
+      const size_t yf = fine_pos(y, g.hy, g.nfy);
+      col[tid] = a.grid + (((size_t)(b * a.K + k) * g.nfz + zf) * g.nfy + yf) * L;
+    }
+  }
+  for (int m = tid; m < L; m += kFftThreads) tw[m] = a.tw[m];
+  __syncthreads();
+  for (int e = tid; e < C * L; e += kFftThreads) {
+    const int l = e % L, c = e / L;
+    lds[l * S + c] = col[c] ? col[c][l] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  RadixSeq<L>::template run<true, C, S, kFftThreads>(lds, tw);
+  const size_t nvox = (size_t)g.Nz * g.Ny * g.Nx;
+  const float sz = a.dz[z];
+  for (int e = tid; e < R * g.Nx; e += kFftThreads) {
+    const int r = e / g.Nx, xq = e - r * g.Nx;
+    const int y = y0 + r;
+    if (y >= g.Ny) continue;
+    const size_t vox = ((size_t)z * g.Ny + y) * g.Nx + xq;
+    const float2 *h = lds + fine_pos(xq, g.hx, L) * S + r * B;
+    float2 acc = make_float2(0.f, 0.f);
+    for (int b = 0; b < B; ++b) {
+      if (a.smaps) acc = cadd(acc, cmulc(h[b], a.smaps[(size_t)a.coils.idx[b] * nvox + vox]));
+      else acc = cadd(acc, h[b]);
+    }
+    const float sc = a.dx[xq] * a.dy[y] * sz;
+    acc.x *= sc;
+    acc.y *= sc;
+    const size_t i = (size_t)k * nvox + vox;
+    if (a.accumulate) acc = cadd(acc, a.xout[i]);
+    a.xout[i] = acc;
+  }
+}
+
 // xout[k] (+)= sum_b conj(S_b) h_{b,k} / deapodisation, h the cropped lines.
 // Grid (ceil(Nx / 64), ceil(Ny / 4), Nz K): the row (k, z, y) comes from the
 // block and thread indices, no per-voxel division.
@@ -477,6 +534,19 @@ hipError_t launch_post_ifftx(const sdn_plan_s &p, const float2 *grid, int K,
   a.dx = p.dinv[0]; a.dy = p.dinv[1]; a.dz = p.dinv[2];
   a.tw = p.tw[0];
   a.rp = p.rp[0];
+  if (fft_len_ct(L) && B <= 16 && 16 % B == 0 && a.g.Nz <= 65535 && K <= 65535) {
+    const int R = 16 / B;
+    dim3 grd((unsigned)((a.g.Ny + R - 1) / R), (unsigned)a.g.Nz, (unsigned)K);
+#define SDN_POST_CT(LEN) \
+  case LEN: hipLaunchKernelGGL(k_ifftx_post_ct<LEN>, grd, dim3(kFftThreads), 0, st, a); break;
+    switch (L) {
+      SDN_POST_CT(64) SDN_POST_CT(96) SDN_POST_CT(128) SDN_POST_CT(160) SDN_POST_CT(192)
+      SDN_POST_CT(224) SDN_POST_CT(256) SDN_POST_CT(288) SDN_POST_CT(320) SDN_POST_CT(384)
+      SDN_POST_CT(400) SDN_POST_CT(448)
+    }
+#undef SDN_POST_CT
+    return hipGetLastError();
+  }
   if (fft_len_ct(L)) {
     CropArgs c;
     c.grid = const_cast<float2 *>(grid);

@@ -340,7 +340,7 @@ __global__ void __launch_bounds__(64) k_spread(SpreadDev a) {
       const int j = raw < 0 ? ~raw : raw;
       const float4 r = a.rec[j];
       const int2 id = a.pidx[j];
-      const float *w = a.wts + (size_t)j * 3 * W;
+      const float *w = a.wts + (size_t)j * wrec_stride(W);
       float *o = bf + lane * RS;
       l0_lane = __float_as_int(r.w);
       int e = (int)((__float_as_uint(r.w) >> 20) & 1023u) - oz;
@@ -464,9 +464,9 @@ __device__ __forceinline__ float value_scale(const unsigned *absmax, bool mix) {
 // Each entry goes through two fetch stages, so that no load waits on
 // another load issued in the same batch: the list stage (two batches
 // ahead) reads the entry and its (frame, original index); the point stage
-// (one batch ahead) reads, through those, the point's first node and
-// weights (wave 0; lanes 0..31 the x/y weights and the node, lanes 32..63
-// the z weights) and its values: with mixing, every wave the residual of
+// (one batch ahead) reads, through those, the point's weight record (wave
+// 0, one half per lane: lanes 0..31 the x/y weights, lanes 32..63 the z
+// weights and the first node) and its values: with mixing, every wave the residual of
 // its coil (lanes 0..31) and the last wave the frame's K basis values for
 // all coils (each half-wave a half of them); else every wave the K values
 // of its coil.  A load instruction costs the memory pipeline about one
@@ -481,8 +481,7 @@ struct MmaList {
 template <int W, bool MIX, int K>
 struct MmaFetch {
   static constexpr int NV = MIX ? (K + 1) / 2 : K;
-  int l0;
-  float w[2 * W];
+  float w[2 * W];     // x, y weights (lanes 0..31); z weights, first node (32..63)
   float2 r;
   float2 v[NV];
 };
@@ -502,15 +501,19 @@ template <int W, bool MIX, int K>
 __device__ __forceinline__ void mma_fetch(const SpreadDev &a, const MmaList &L, int grp, bool coil_ok,
                                           bool v_wave, int wv, int lane, MmaFetch<W, MIX, K> &f) {
   const bool ok = L.ok;
-  const float *w = a.wts + (size_t)L.j * 3 * W;
   if (wv == 0) {
-    const float *wl = w + (lane < kMmaBatch ? 0 : 2 * W);
+    // one half of the point's record per lane, 16-byte loads: lanes 0..31
+    // the x and y weights, lanes 32..63 the z weights and the first node
+    static_assert((2 * W) % 4 == 0, "record halves are whole float4s");
+    const float4 *wl = reinterpret_cast<const float4 *>(
+        a.wts + (size_t)L.j * wrec_stride(W) + (lane < kMmaBatch ? 0 : 2 * W));
 #pragma unroll
-    for (int i = 0; i < W; ++i) f.w[i] = ok ? wl[i] : 0.f;
-    if (lane < kMmaBatch) {
-      f.l0 = __float_as_int(a.rec[L.j].w);
-#pragma unroll
-      for (int i = 0; i < W; ++i) f.w[W + i] = ok ? wl[W + i] : 0.f;
+    for (int i = 0; i < W / 2; ++i) {
+      const float4 v = ok ? wl[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+      f.w[4 * i] = v.x;
+      f.w[4 * i + 1] = v.y;
+      f.w[4 * i + 2] = v.z;
+      f.w[4 * i + 3] = v.w;
     }
   }
   const bool vok = ok && coil_ok;
@@ -578,17 +581,17 @@ __global__ void __launch_bounds__(64 * NG) k_spread_mma(SpreadDev a, const unsig
   auto stage = [&](int bf) {
     if (wv == 0) {
       if (lane < kMmaBatch) {
-        const unsigned u = (unsigned)f.l0;
-        const int sx = win_shift(ox, (int)(u & 1023u), a.nfx, W);
-        const int sy = win_shift(oy, (int)((u >> 10) & 1023u), a.nfy, W);
-        const int sz = win_shift(oz, (int)((u >> 20) & 1023u), a.nfz, W);
-        shifts[bf][p] = (sx + kWinPad) | ((sy + kWinPad) << 8) | ((sz + kWinPad) << 16);
 #pragma unroll
         for (int i = 0; i < W; ++i) {
           wrow[bf][0][p][kWinPad + i] = f.w[i];
           wrow[bf][1][p][kWinPad + i] = f.w[W + i];
         }
       } else {
+        const unsigned u = __float_as_uint(f.w[W]);
+        const int sx = win_shift(ox, (int)(u & 1023u), a.nfx, W);
+        const int sy = win_shift(oy, (int)((u >> 10) & 1023u), a.nfy, W);
+        const int sz = win_shift(oz, (int)((u >> 20) & 1023u), a.nfz, W);
+        shifts[bf][p] = (sx + kWinPad) | ((sy + kWinPad) << 8) | ((sz + kWinPad) << 16);
 #pragma unroll
         for (int i = 0; i < W; ++i) wrow[bf][2][p][kWinPad + i] = f.w[i];
       }

@@ -275,17 +275,20 @@ __global__ void k_weights(const float4 *__restrict__ rec, int M, KerCoef kc,
   if (j >= M) return;
   const float4 r = rec[j];
   float w[W];
-  float *o = wts + (size_t)j * 3 * W;
+  float *o = wts + (size_t)j * wrec_stride(W);
   const float tc[3] = {r.x, r.y, r.z};
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     axis_weights<W, NC>(tc[d], kc, w);
 #pragma unroll
     for (int i = 0; i < W; ++i) {
-      o[d * W + i] = w[i];
+      o[(d < 2 ? d * W : 2 * W) + i] = w[i];
       wts_t[(size_t)(d * W + i) * M + j] = w[i];
     }
   }
+  o[3 * W] = r.w;
+#pragma unroll
+  for (int i = 3 * W + 1; i < wrec_stride(W); ++i) o[i] = 0.f;
   wts_t[(size_t)3 * W * M + j] = r.w;
 }
 
@@ -552,7 +555,7 @@ sdn_status sdn_plan_create(sdn_plan *out, const int64_t shape[3], const float *t
       s = hip_check(hipGetLastError(), "plan placement kernel");
     }
     // per-point kernel weights
-    if (s == SDN_OK) s = dalloc(&p->wts, (size_t)m * 3 * p->W, "plan weights");
+    if (s == SDN_OK) s = dalloc(&p->wts, (size_t)m * wrec_stride(p->W), "plan weights");
     if (s == SDN_OK) s = dalloc(&p->wts_t, (size_t)m * (3 * p->W + 1), "plan weights");
     if (s == SDN_OK) {
       if (p->W == 4)

@@ -18,6 +18,9 @@ constexpr int kMaxK = 8;        // subspace channels
 constexpr int kMaxRadices = 12; // FFT passes per axis
 constexpr int kItemCap = 2048;  // points per interpolation work item
 constexpr int kSpreadCap = 8192; // list entries per spreading work item
+// Per-point weight record of the spreading kernels (W even): [x W][y W] then
+// [z W][first node][W - 1 zeros], two 16-byte-aligned halves of 2W floats.
+constexpr int wrec_stride(int W) { return 4 * W; }
 
 // Piecewise-polynomial Kaiser-Bessel kernel: for a point with fractional
 // offset t in [0,1), the weight of its i-th node is
@@ -95,7 +98,8 @@ struct sdn_plan_s {
   int2 *pidx = nullptr;      // (frame, original index)
   int32_t *frame_user = nullptr;  // frame per point, user order
   int4 *work = nullptr;      // interpolation items: (tile, start, count, 0)
-  float *wts = nullptr;      // per point (plan order): W weights per axis, x then y then z
+  float *wts = nullptr;      // per point (plan order), 4W floats: x and y weights, then z
+                             // weights, the packed first node's bits and W - 1 zeros
   float *wts_t = nullptr;    // the same transposed, [3W][M], then [M] packed first-node bits:
                              // consecutive points' values are contiguous (interpolation)
   int *vlist = nullptr;      // spreading lists: plan indices of the points whose support

@@ -199,7 +199,7 @@ __global__ void __launch_bounds__(kIThreads) k_interp(InterpDev a) {
         const float wt = a.w ? a.w[orig] : 1.f;
         my_loss += (double)wt * ((double)df.x * df.x + (double)df.y * df.y);
         const float sw = a.rscale * wt;
-        a.r_plan[(size_t)grp * a.M + wi.y + q] = make_float2(sw * df.x, sw * df.y);
+        a.r_plan[(size_t)(wi.y + q) * gridDim.y + grp] = make_float2(sw * df.x, sw * df.y);
       } else {
         a.y[(size_t)grp * a.M + orig] = acc[i];
       }
@@ -354,7 +354,8 @@ __global__ void __launch_bounds__(64) k_spread(SpreadDev a) {
       }
       const int col = a.src_plan ? j : id.y;
       if constexpr (MIX) {
-        const float2 rv = a.src[(size_t)grp * a.M + col];
+        const float2 rv = a.src_plan ? a.src[(size_t)j * a.groups + grp]
+                                     : a.src[(size_t)grp * a.M + col];
 #pragma unroll
         for (int kk = 0; kk < K; ++kk) {
           const float2 v = cmulc(rv, a.V[(size_t)id.x * K + kk]);
@@ -482,7 +483,7 @@ template <int W, bool MIX, int K>
 struct MmaFetch {
   static constexpr int NV = MIX ? (K + 1) / 2 : K;
   float w[2 * W];     // x, y weights (lanes 0..31); z weights, first node (32..63)
-  float2 r;
+  float2 r[2];        // mixing: residuals of coil slots h and h + 2 (h = lane / 32)
   float2 v[NV];
 };
 
@@ -497,9 +498,10 @@ __device__ __forceinline__ void mma_list(const SpreadDev &a, const int4 &it, int
   L.id = (L.ok && (all_lanes || lane < kMmaBatch)) ? a.vinfo[it.y + e] : make_int2(0, 0);
 }
 
-template <int W, bool MIX, int K>
+template <int W, bool MIX, int K, int NG>
 __device__ __forceinline__ void mma_fetch(const SpreadDev &a, const MmaList &L, int grp, bool coil_ok,
-                                          bool v_wave, int wv, int lane, MmaFetch<W, MIX, K> &f) {
+                                          bool v_wave, bool r_wave, int g0, int wv, int lane,
+                                          MmaFetch<W, MIX, K> &f) {
   const bool ok = L.ok;
   if (wv == 0) {
     // one half of the point's record per lane, 16-byte loads: lanes 0..31
@@ -519,7 +521,19 @@ __device__ __forceinline__ void mma_fetch(const SpreadDev &a, const MmaList &L, 
   const bool vok = ok && coil_ok;
   const int col = a.src_plan ? L.j : L.id.y;
   if constexpr (MIX) {
-    if (lane < kMmaBatch) f.r = vok ? a.src[(size_t)grp * a.M + col] : make_float2(0.f, 0.f);
+    if (r_wave) {
+      // the residuals of all coils of the workgroup: in plan order a point's
+      // coils are side by side, so both half-waves read the same lines
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int c = (lane >> 5) + 2 * i;
+        const int g = g0 + c;
+        const bool rok = ok && c < NG && g < a.groups;
+        f.r[i] = !rok ? make_float2(0.f, 0.f)
+                      : a.src_plan ? a.src[(size_t)L.j * a.groups + g]
+                                   : a.src[(size_t)g * a.M + L.id.y];
+      }
+    }
     if (v_wave) {
       const int k0 = (lane >> 5) * f.NV;
 #pragma unroll
@@ -545,6 +559,7 @@ __global__ void __launch_bounds__(64 * NG) k_spread_mma(SpreadDev a, const unsig
   __shared__ float wrow[2][3][kMmaBatch][kWinLen];
   __shared__ __align__(16) float vals[2][NG][kMmaBatch][2 * KP];
   __shared__ __align__(16) float2 vbas[2][kMmaBatch][KP];   // mixing: the frame's basis values
+  __shared__ float2 rsd[2][NG][kMmaBatch];                    // mixing: each coil's residual
   __shared__ int shifts[2][kMmaBatch];
   __shared__ uint4 sA[2][2][4][64];   // [buffer][hi/lo][row tile][lane]: (y,x) operand fragments
   const int4 it = a.items[blockIdx.x];
@@ -552,6 +567,8 @@ __global__ void __launch_bounds__(64 * NG) k_spread_mma(SpreadDev a, const unsig
   const int grp = blockIdx.y * NG + wv;
   const bool coil_ok = grp < a.groups;
   const bool v_wave = MIX && wv == NG - 1;   // loads the basis values for all coils
+  const bool r_wave = MIX && wv == (NG > 1 ? 1 : 0);   // loads the residuals of all coils
+  const int g0 = blockIdx.y * NG;
   const int bzi = it.x / (a.nbx * a.nby);
   const int rem = it.x - bzi * (a.nbx * a.nby);
   const int byi = rem / a.nbx, bxi = rem - byi * a.nbx;
@@ -575,7 +592,6 @@ __global__ void __launch_bounds__(64 * NG) k_spread_mma(SpreadDev a, const unsig
 
   MmaList L;
   MmaFetch<W, MIX, K> f;
-  float2 r_staged = make_float2(0.f, 0.f);   // mixing: residual of the staged batch
   // stage the fetched batch into buffer bf: wave 0 the point data; with
   // mixing the basis values (last wave), else every wave its coil's values
   auto stage = [&](int bf) {
@@ -603,7 +619,13 @@ __global__ void __launch_bounds__(64 * NG) k_spread_mma(SpreadDev a, const unsig
         for (int i = 0; i < f.NV; ++i)
           if (k0 + i < K) vbas[bf][p][k0 + i] = f.v[i];
       }
-      r_staged = f.r;
+      if (r_wave) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          const int c = (lane >> 5) + 2 * i;
+          if (c < NG) rsd[bf][c][p] = f.r[i];
+        }
+      }
     } else {
       if (lane < kMmaBatch) {
 #pragma unroll
@@ -621,7 +643,7 @@ __global__ void __launch_bounds__(64 * NG) k_spread_mma(SpreadDev a, const unsig
       if (lane < kMmaBatch) {
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-          const float2 v = cmulc(r_staged, vbas[bf][p][k]);
+          const float2 v = cmulc(rsd[bf][wv][p], vbas[bf][p][k]);
           vals[bf][wv][p][k] = v.x * s;
           vals[bf][wv][p][KP + k] = v.y * s;
         }
@@ -632,15 +654,15 @@ __global__ void __launch_bounds__(64 * NG) k_spread_mma(SpreadDev a, const unsig
   // list two batches ahead
   auto advance = [&](int e) {
     if (e < it.z) {
-      mma_fetch<W, MIX, K>(a, L, grp, coil_ok, v_wave, wv, lane, f);
-      if (e + kMmaBatch < it.z) mma_list(a, it, e + kMmaBatch + p, v_wave, lane, L);
+      mma_fetch<W, MIX, K, NG>(a, L, grp, coil_ok, v_wave, r_wave, g0, wv, lane, f);
+      if (e + kMmaBatch < it.z) mma_list(a, it, e + kMmaBatch + p, v_wave || r_wave, lane, L);
     }
   };
 
   if (it.z > 0) {
-    mma_list(a, it, p, v_wave, lane, L);
-    mma_fetch<W, MIX, K>(a, L, grp, coil_ok, v_wave, wv, lane, f);
-    if (kMmaBatch < it.z) mma_list(a, it, kMmaBatch + p, v_wave, lane, L);
+    mma_list(a, it, p, v_wave || r_wave, lane, L);
+    mma_fetch<W, MIX, K, NG>(a, L, grp, coil_ok, v_wave, r_wave, g0, wv, lane, f);
+    if (kMmaBatch < it.z) mma_list(a, it, kMmaBatch + p, v_wave || r_wave, lane, L);
   }
   __syncthreads();   // rows zeroed
   if (it.z > 0) {
@@ -972,6 +994,7 @@ hipError_t spread_k(const SpreadDev &d, int K, dim3 grd, hipStream_t st) {
 
 hipError_t launch_spread(const sdn_plan_s &p, const SpreadArgs &a, hipStream_t st) {
   if (p.M == 0 || p.sitems == nullptr) return hipErrorInvalidValue;
+  if (a.src_plan_order && a.V == nullptr) return hipErrorInvalidValue;
   if (p.nslots > 0 && a.part == nullptr) return hipErrorInvalidValue;
   if (a.K < 1 || a.K > kMaxK) return hipErrorInvalidValue;
   SpreadDev d;

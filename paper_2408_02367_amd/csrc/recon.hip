@@ -60,7 +60,7 @@ __global__ void k_weighted_plan(const int2 *__restrict__ pidx, int M, const floa
   const int orig = pidx[j].y;
   const float s = w ? scale * w[orig] : scale;
   const float2 v = y[(size_t)g * M + orig];
-  out[(size_t)g * M + j] = make_float2(s * v.x, s * v.y);
+  out[(size_t)j * gridDim.y + g] = make_float2(s * v.x, s * v.y);
 }
 
 __global__ void __launch_bounds__(kRedThreads) k_axpy_dot(float2 *__restrict__ y,

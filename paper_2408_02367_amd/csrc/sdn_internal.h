@@ -155,7 +155,7 @@ constexpr int kDotBlocks = 1024;
 hipError_t launch_dot(const float2 *a, const float2 *b, size_t n, double *part, hipStream_t st);
 // *out = scale * sum(part[0 .. n))
 hipError_t launch_sum(const double *part, int n, double scale, double *out, hipStream_t st);
-// out[g][j] = scale w[orig(j)] y[g][orig(j)], plan order, for g < groups
+// out[j][g] = scale w[orig(j)] y[g][orig(j)], plan order, for g < groups
 hipError_t launch_weighted_plan(const sdn_plan_s &p, const float2 *y, int groups, const float *w,
                                 float scale, float2 *out, hipStream_t st);
 // y += lam x, and part = partials of Re <x, y> (after the update)
@@ -213,7 +213,7 @@ struct InterpArgs {
   float rscale;
   const float2 *d;  // [groups][M] user order, or null
   const float *w;   // [M] user order, or null
-  float2 *r_plan;   // [groups][M] plan order
+  float2 *r_plan;   // [M][groups] plan order, a point's coils side by side
   double *loss;
 };
 hipError_t launch_interp(const sdn_plan_s &p, const InterpArgs &a, hipStream_t st);
@@ -230,7 +230,8 @@ struct SpreadArgs {
   int groups;
   int K;
   const float2 *V;    // [T][K] or null
-  const float2 *src;  // [rows][M]
+  const float2 *src;  // user order: [rows][M]; plan order (mix mode only):
+                      // [M][groups], a point's coils side by side
   bool src_plan_order;
 };
 hipError_t launch_spread(const sdn_plan_s &p, const SpreadArgs &a, hipStream_t st);

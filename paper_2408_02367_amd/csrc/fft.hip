@@ -305,18 +305,35 @@ k_pre_fftx_ct(PreArgs a, float inv_nx, float inv_p) {
     lds[((g.Nx - g.hx) + r) * S + c] = make_float2(0.f, 0.f);
   }
   __syncthreads();
-  for (int e = tid; e < C * g.Nx; e += kFftThreads) {
-    const int c = qdiv(e, inv_nx);
-    const int xq = e - c * g.Nx;
-    float2 v = make_float2(0.f, 0.f);
-    if (xrow[c]) {
-      v = xrow[c][xq];
-      if (srow[c]) v = cmul(srow[c][xq], v);
+  // every thread issues all its loads before using any (Nx <= L, so
+  // C Nx <= C L elements cover the workgroup)
+  constexpr int NE = L * C / kFftThreads;
+  float2 xv[NE], sv[NE];
+#pragma unroll
+  for (int i = 0; i < NE; ++i) {
+    const int e = tid + i * kFftThreads;
+    xv[i] = sv[i] = make_float2(0.f, 0.f);
+    if (e < C * g.Nx) {
+      const int c = qdiv(e, inv_nx);
+      const int xq = e - c * g.Nx;
+      if (xrow[c]) {
+        xv[i] = xrow[c][xq];
+        sv[i] = srow[c] ? srow[c][xq] : make_float2(1.f, 0.f);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NE; ++i) {
+    const int e = tid + i * kFftThreads;
+    if (e < C * g.Nx) {
+      const int c = qdiv(e, inv_nx);
+      const int xq = e - c * g.Nx;
+      float2 v = cmul(sv[i], xv[i]);
       const float sc = a.dx[xq] * scyz[c];
       v.x *= sc;
       v.y *= sc;
+      lds[fine_pos(xq, g.hx, L) * S + c] = v;
     }
-    lds[fine_pos(xq, g.hx, L) * S + c] = v;
   }
   __syncthreads();
   RadixSeq<L>::template run<false, C, S, kFftThreads>(lds, tw);
@@ -360,9 +377,20 @@ k_ifftx_crop_ct(CropArgs a, float inv_nx) {
   }
   for (int m = tid; m < L; m += kFftThreads) tw[m] = a.tw[m];
   __syncthreads();
-  for (int e = tid; e < C * L; e += kFftThreads) {
-    const int l = e % L, c = e / L;
-    lds[l * S + c] = row[c] ? row[c][l] : make_float2(0.f, 0.f);
+  {
+    constexpr int NE = L * C / kFftThreads;
+    float2 v[NE];
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+      const int e = tid + i * kFftThreads;
+      const int l = e % L, c = e / L;
+      v[i] = row[c] ? row[c][l] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+      const int e = tid + i * kFftThreads;
+      lds[(e % L) * S + e / L] = v[i];
+    }
   }
   __syncthreads();
   RadixSeq<L>::template run<true, C, S, kFftThreads>(lds, tw);
@@ -402,9 +430,20 @@ k_ifftx_post_ct(PostArgs a) {
   }
   for (int m = tid; m < L; m += kFftThreads) tw[m] = a.tw[m];
   __syncthreads();
-  for (int e = tid; e < C * L; e += kFftThreads) {
-    const int l = e % L, c = e / L;
-    lds[l * S + c] = col[c] ? col[c][l] : make_float2(0.f, 0.f);
+  {
+    constexpr int NE = L * C / kFftThreads;
+    float2 v[NE];
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+      const int e = tid + i * kFftThreads;
+      const int l = e % L, c = e / L;
+      v[i] = col[c] ? col[c][l] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+      const int e = tid + i * kFftThreads;
+      lds[(e % L) * S + e / L] = v[i];
+    }
   }
   __syncthreads();
   RadixSeq<L>::template run<true, C, S, kFftThreads>(lds, tw);
@@ -417,6 +456,7 @@ k_ifftx_post_ct(PostArgs a) {
     const size_t vox = ((size_t)z * g.Ny + y) * g.Nx + xq;
     const float2 *h = lds + fine_pos(xq, g.hx, L) * S + r * B;
     float2 acc = make_float2(0.f, 0.f);
+#pragma unroll 4
     for (int b = 0; b < B; ++b) {
       if (a.smaps) acc = cadd(acc, cmulc(h[b], a.smaps[(size_t)a.coils.idx[b] * nvox + vox]));
       else acc = cadd(acc, h[b]);

@@ -108,13 +108,24 @@ __global__ void __launch_bounds__(kIThreads) k_interp(InterpDev a) {
   for (int i = 0; i < kPts; ++i) acc[i] = make_float2(0.f, 0.f);
   for (int k = 0; k < a.K; ++k) {
     const float2 *gp = a.grid + (size_t)(grp * a.K + k) * g.G;
-    for (int e = tid; e < ncell; e += kIThreads) {
-      const int row = fdiv(e, a.inv_px);
-      const int cx = e - row * PX;
-      const int cz = fdiv(row, a.inv_py);
-      const int cy = row - cz * PY;
-      const int gx = wrap(ox + cx, g.nfx), gy = wrap(oy + cy, g.nfy), gz = wrap(oz + cz, g.nfz);
-      tile[e] = gp[((size_t)gz * g.nfy + gy) * g.nfx + gx];
+    // four loads in flight per thread before their LDS stores
+    for (int e0 = tid; e0 < ncell; e0 += 4 * kIThreads) {
+      float2 v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = e0 + u * kIThreads;
+        if (e < ncell) {
+          const int row = fdiv(e, a.inv_px);
+          const int cx = e - row * PX;
+          const int cz = fdiv(row, a.inv_py);
+          const int cy = row - cz * PY;
+          const int gx = wrap(ox + cx, g.nfx), gy = wrap(oy + cy, g.nfy), gz = wrap(oz + cz, g.nfz);
+          v[u] = gp[((size_t)gz * g.nfy + gy) * g.nfx + gx];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (e0 + u * kIThreads < ncell) tile[e0 + u * kIThreads] = v[u];
     }
     __syncthreads();
 #pragma unroll 1

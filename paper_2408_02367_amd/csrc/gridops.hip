@@ -779,12 +779,22 @@ __global__ void __launch_bounds__(64 * NG) k_spread_mma(SpreadDev a, const unsig
   }
 }
 
-// Largest |component| of n floats, as float bits (non-negative floats order
-// like their bit patterns) into *out, which starts at zero.
-__global__ void __launch_bounds__(256) k_absmax(const float *x, size_t n, unsigned *out) {
+// Largest |component| of n complex values, as float bits (non-negative
+// floats order like their bit patterns) into *out, which starts at zero.
+// Four 8-byte loads per thread are in flight per step.
+__global__ void __launch_bounds__(256) k_absmax(const float2 *x, size_t n, unsigned *out) {
   float m = 0.f;
-  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
-    m = fmaxf(m, fabsf(x[i]));
+  const size_t stride = (size_t)gridDim.x * 256;
+  for (size_t i0 = (size_t)blockIdx.x * 256 + threadIdx.x; i0 < n; i0 += 4 * stride) {
+    float2 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const size_t i = i0 + u * stride;
+      v[u] = i < n ? x[i] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) m = fmaxf(m, fmaxf(fabsf(v[u].x), fabsf(v[u].y)));
+  }
   for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
   if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(m));
 }
@@ -807,6 +817,7 @@ __global__ void __launch_bounds__(kThreads) k_spread_reduce(SpreadDev a, const i
     const int gx = ox + (lane & (kSB - 1)), gy = oy + lane / kSB, gz = oz + c;
     if (gx >= a.nfx || gy >= a.nfy || gz >= a.nfz) continue;
     float sr = 0.f, si = 0.f;
+#pragma unroll 8
     for (int q = 0; q < sp.z; ++q) {
       const float2 v = a.part[(((size_t)(sp.y + q) * a.groups + grp) * K + kk) * kSBCells + cell];
       sr += v.x;
@@ -1031,12 +1042,12 @@ hipError_t launch_spread(const sdn_plan_s &p, const SpreadArgs &a, hipStream_t s
   if (spread_engine_for(p, a.K, a.groups)) {
     // value scale: the largest input component (and of V when mixing)
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, p.absmax, 2);
-    const size_t nsrc = (size_t)a.groups * (mix ? 1 : a.K) * p.M * 2;
-    const unsigned nblk = (unsigned)std::min<size_t>(2048, (nsrc + 1023) / 1024);
-    hipLaunchKernelGGL(k_absmax, dim3(nblk), dim3(256), 0, st, (const float *)a.src, nsrc, p.absmax);
+    const size_t nsrc = (size_t)a.groups * (mix ? 1 : a.K) * p.M;
+    const unsigned nblk = (unsigned)std::min<size_t>(8192, (nsrc + 1023) / 1024);
+    hipLaunchKernelGGL(k_absmax, dim3(nblk), dim3(256), 0, st, a.src, nsrc, p.absmax);
     if (mix)
-      hipLaunchKernelGGL(k_absmax, dim3(1), dim3(256), 0, st, (const float *)a.V,
-                         (size_t)p.T * a.K * 2, p.absmax + 1);
+      hipLaunchKernelGGL(k_absmax, dim3(1), dim3(256), 0, st, a.V, (size_t)p.T * a.K,
+                         p.absmax + 1);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     switch (p.W) {

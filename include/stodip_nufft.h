@@ -73,8 +73,9 @@ typedef struct {
                               >= 2 channels, else the gather), SDN_SPREAD_GATHER
                               (vector ALU gather into registers) or
                               SDN_SPREAD_MATRIX (matrix cores, split fp16 products
-                              with FP32 accumulation; needs every fine axis >= 16
-                              and >= 2 channels per call, else the gather runs)     */
+                              with FP32 accumulation; for the subspace calls with
+                              >= 2 channels and every fine axis >= 16, else the
+                              gather runs; the plain type-1 call always gathers)   */
 } sdn_opts;
 
 /* Values of sdn_opts.spread_engine. */

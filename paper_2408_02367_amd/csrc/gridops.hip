@@ -478,12 +478,11 @@ __device__ __forceinline__ float value_scale(const unsigned *absmax, bool mix) {
 // ahead) reads the entry and its (frame, original index); the point stage
 // (one batch ahead) reads, through those, the point's weight record (wave
 // 0, one half per lane: lanes 0..31 the x/y weights, lanes 32..63 the z
-// weights and the first node) and its values: with mixing, every wave the residual of
-// its coil (lanes 0..31) and the last wave the frame's K basis values for
-// all coils (each half-wave a half of them); else every wave the K values
-// of its coil.  A load instruction costs the memory pipeline about one
-// cycle per cache line it touches, so each scattered value is loaded once
-// per workgroup, not once per coil.
+// weights and the first node), the residuals of all the workgroup's coils
+// (wave 1, or 0 for a single coil) and the frame's K basis values (the
+// last wave, each half-wave a half of them).  A load instruction costs the
+// memory pipeline about one cycle per cache line it touches, so each
+// scattered value is loaded once per workgroup, not once per coil.
 struct MmaList {
   int j;      // plan index of the point
   int2 id;    // (frame, original index)
@@ -492,7 +491,7 @@ struct MmaList {
 
 template <int W, bool MIX, int K>
 struct MmaFetch {
-  static constexpr int NV = MIX ? (K + 1) / 2 : K;
+  static constexpr int NV = (K + 1) / 2;   // basis values per lane (half of K)
   float w[2 * W];     // x, y weights (lanes 0..31); z weights, first node (32..63)
   float2 r[2];        // mixing: residuals of coil slots h and h + 2 (h = lane / 32)
   float2 v[NV];
@@ -529,9 +528,10 @@ __device__ __forceinline__ void mma_fetch(const SpreadDev &a, const MmaList &L, 
       f.w[4 * i + 3] = v.w;
     }
   }
-  const bool vok = ok && coil_ok;
-  const int col = a.src_plan ? L.j : L.id.y;
-  if constexpr (MIX) {
+  static_assert(MIX, "the matrix-core spreading serves the subspace-mixing calls");
+  (void)grp;
+  (void)coil_ok;
+  {
     if (r_wave) {
       // the residuals of all coils of the workgroup: in plan order a point's
       // coils are side by side, so both half-waves read the same lines
@@ -550,12 +550,6 @@ __device__ __forceinline__ void mma_fetch(const SpreadDev &a, const MmaList &L, 
 #pragma unroll
       for (int i = 0; i < f.NV; ++i)
         f.v[i] = k0 + i < K ? a.V[(size_t)L.id.x * K + k0 + i] : make_float2(0.f, 0.f);
-    }
-  } else {
-    if (lane < kMmaBatch) {
-#pragma unroll
-      for (int k = 0; k < K; ++k)
-        f.v[k] = vok ? a.src[(size_t)(grp * K + k) * a.M + col] : make_float2(0.f, 0.f);
     }
   }
 }
@@ -603,8 +597,8 @@ __global__ void __launch_bounds__(64 * NG) k_spread_mma(SpreadDev a, const unsig
 
   MmaList L;
   MmaFetch<W, MIX, K> f;
-  // stage the fetched batch into buffer bf: wave 0 the point data; with
-  // mixing the basis values (last wave), else every wave its coil's values
+  // stage the fetched batch into buffer bf: wave 0 the point data, the last
+  // wave the basis values, wave 1 (or 0) the coils' residuals
   auto stage = [&](int bf) {
     if (wv == 0) {
       if (lane < kMmaBatch) {
@@ -635,14 +629,6 @@ __global__ void __launch_bounds__(64 * NG) k_spread_mma(SpreadDev a, const unsig
         for (int i = 0; i < 2; ++i) {
           const int c = (lane >> 5) + 2 * i;
           if (c < NG) rsd[bf][c][p] = f.r[i];
-        }
-      }
-    } else {
-      if (lane < kMmaBatch) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-          vals[bf][wv][p][k] = f.v[k].x * s;
-          vals[bf][wv][p][KP + k] = f.v[k].y * s;
         }
       }
     }
@@ -988,8 +974,9 @@ hipError_t spread_mma(const SpreadDev &d, int K, dim3 grd, const unsigned *absma
 
 }  // namespace
 
-// The matrix-core spreading needs every fine axis >= 16 cells (no support
-// touches both ends of a block) and at least two channels per group.
+// The matrix-core spreading serves the subspace-mixing calls; it needs every
+// fine axis >= 16 cells (no support touches both ends of a block) and at
+// least two channels per coil.
 bool spread_engine_for(const sdn_plan_s &p, int K, int groups) {
   if (p.spread_engine == SDN_SPREAD_GATHER) return false;
   // automatic choice: the matrix cores pay once several coils share the
@@ -1039,21 +1026,20 @@ hipError_t launch_spread(const sdn_plan_s &p, const SpreadArgs &a, hipStream_t s
   const bool mix = a.V != nullptr;
   dim3 grd((unsigned)p.nsitems, (unsigned)a.groups);
   hipError_t e;
-  if (spread_engine_for(p, a.K, a.groups)) {
-    // value scale: the largest input component (and of V when mixing)
+  if (mix && spread_engine_for(p, a.K, a.groups)) {
+    // value scale: the largest component of the residuals and of V
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, p.absmax, 2);
-    const size_t nsrc = (size_t)a.groups * (mix ? 1 : a.K) * p.M;
+    const size_t nsrc = (size_t)a.groups * p.M;
     const unsigned nblk = (unsigned)std::min<size_t>(8192, (nsrc + 1023) / 1024);
     hipLaunchKernelGGL(k_absmax, dim3(nblk), dim3(256), 0, st, a.src, nsrc, p.absmax);
-    if (mix)
-      hipLaunchKernelGGL(k_absmax, dim3(1), dim3(256), 0, st, a.V, (size_t)p.T * a.K,
-                         p.absmax + 1);
+    hipLaunchKernelGGL(k_absmax, dim3(1), dim3(256), 0, st, a.V, (size_t)p.T * a.K,
+                       p.absmax + 1);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     switch (p.W) {
-      case 4: e = mix ? spread_mma<4, true>(d, a.K, grd, p.absmax, st) : spread_mma<4, false>(d, a.K, grd, p.absmax, st); break;
-      case 8: e = mix ? spread_mma<8, true>(d, a.K, grd, p.absmax, st) : spread_mma<8, false>(d, a.K, grd, p.absmax, st); break;
-      default: e = mix ? spread_mma<6, true>(d, a.K, grd, p.absmax, st) : spread_mma<6, false>(d, a.K, grd, p.absmax, st); break;
+      case 4: e = spread_mma<4, true>(d, a.K, grd, p.absmax, st); break;
+      case 8: e = spread_mma<8, true>(d, a.K, grd, p.absmax, st); break;
+      default: e = spread_mma<6, true>(d, a.K, grd, p.absmax, st); break;
     }
   } else {
     switch (p.W) {

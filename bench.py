@@ -149,8 +149,9 @@ def _log(msg):
 def main():
     a = _args()
     if a.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported "
-              "(the coil axis would shard across GPUs, see the design notes)", file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported (the coil "
+              "axis would shard across GPUs, with one all-reduce of the image gradient per "
+              "step)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -276,6 +277,9 @@ def main():
                nfz=info["fine"][0], nfy=info["fine"][1], nfx=info["fine"][2])
     sb = stage_bytes(geo)
     sf = stage_flops(geo, info["W"])
+    # on-chip bytes of the interpolation: every (point, channel) reads its
+    # W^3 cells (8 B each) from the LDS tile
+    sl = {"interp": 8 * info["W"] ** 3 * M * P}
     per_stage = {}
     for s, (ms, n) in stages.items():
         avg = ms / n
@@ -283,8 +287,13 @@ def main():
                         "avg_launch_ms": round(avg, 4)}
         if s in sb:
             per_stage[s]["algo_GBps"] = round(sb[s] / (avg * 1e-3) / 1e9, 1)
+            per_stage[s]["hbm_frac"] = round(sb[s] / (avg * 1e-3) / 8.0e12, 4)
         if s in sf:
             per_stage[s]["TFLOPs"] = round(sf[s] / (avg * 1e-3) / 1e12, 2)
+            # against the FP32 vector peak (157.3 TFLOP/s with packed FP32)
+            per_stage[s]["fp32_vector_frac"] = round(sf[s] / (avg * 1e-3) / 157.3e12, 4)
+        if s in sl:
+            per_stage[s]["lds_read_TBps"] = round(sl[s] / (avg * 1e-3) / 1e12, 1)
     dom = max((s for s in stages if s in sb), key=lambda s: stages[s][0])
     dom_avg_s = stages[dom][0] / stages[dom][1] * 1e-3
     if dom == "spread" and info["spread_engine"] == "matrix":

@@ -781,8 +781,13 @@ __global__ void __launch_bounds__(256) k_absmax(const float2 *x, size_t n, unsig
 #pragma unroll
     for (int u = 0; u < 4; ++u) m = fmaxf(m, fmaxf(fabsf(v[u].x), fabsf(v[u].y)));
   }
+  // one atomic per workgroup: the waves' maxima meet in LDS first
+  __shared__ float wmax[4];
   for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
-  if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(m));
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    atomicMax(out, __float_as_uint(fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]))));
 }
 
 __global__ void k_zero_u32(unsigned *p, int n) {
@@ -1030,7 +1035,7 @@ hipError_t launch_spread(const sdn_plan_s &p, const SpreadArgs &a, hipStream_t s
     // value scale: the largest component of the residuals and of V
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, p.absmax, 2);
     const size_t nsrc = (size_t)a.groups * p.M;
-    const unsigned nblk = (unsigned)std::min<size_t>(8192, (nsrc + 1023) / 1024);
+    const unsigned nblk = (unsigned)std::min<size_t>(2048, (nsrc + 1023) / 1024);
     hipLaunchKernelGGL(k_absmax, dim3(nblk), dim3(256), 0, st, a.src, nsrc, p.absmax);
     hipLaunchKernelGGL(k_absmax, dim3(1), dim3(256), 0, st, a.V, (size_t)p.T * a.K,
                        p.absmax + 1);

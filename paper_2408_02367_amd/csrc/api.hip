@@ -226,6 +226,7 @@ sdn_status normal_pass(sdn_plan_s *p, const float2 *x, int K, const float2 *smap
     a.w = w;
     a.r_plan = p->kbuf;
     a.loss = loss;
+    a.rmax = p->absmax;
     SDN_STAGE(p, SDN_STAGE_INTERP, launch_interp(*p, a, st), "interpolation + weighting");
     if (!adjoint) continue;
     SDN_TRY(ensure_part(p, bc, K));
@@ -237,6 +238,7 @@ sdn_status normal_pass(sdn_plan_s *p, const float2 *x, int K, const float2 *smap
     s.V = V;
     s.src = p->kbuf;
     s.src_plan_order = true;
+    s.src_max_ready = true;   // recorded by the interpolation above
     SDN_STAGE(p, SDN_STAGE_SPREAD, launch_spread(*p, s, st), "spreading");
     SDN_TRY(adjoint_grid(p, K, smaps, coils, bc, out, (accumulate || b0 > 0) ? 1 : 0, st));
   }
@@ -424,6 +426,7 @@ sdn_status sdn_mrf_dc_grad(sdn_plan p, const void *x, int K, const void *smaps, 
     a.w = w;
     a.r_plan = p->kbuf;
     a.loss = loss;
+    a.rmax = p->absmax;
     SDN_STAGE(p, SDN_STAGE_INTERP, launch_interp(*p, a, st), "interpolation + residual");
     SDN_TRY(ensure_part(p, bc, K));
     SpreadArgs s{};
@@ -434,6 +437,7 @@ sdn_status sdn_mrf_dc_grad(sdn_plan p, const void *x, int K, const void *smaps, 
     s.V = (const float2 *)V;
     s.src = p->kbuf;
     s.src_plan_order = true;
+    s.src_max_ready = true;   // recorded by the interpolation above
     SDN_STAGE(p, SDN_STAGE_SPREAD, launch_spread(*p, s, st), "spreading");
     SDN_TRY(adjoint_grid(p, K, (const float2 *)smaps, coils, bc, (float2 *)grad, b0 > 0 ? 1 : 0,
                          st));

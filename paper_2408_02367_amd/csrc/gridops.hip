@@ -71,6 +71,7 @@ struct InterpDev {
   float2 *r_plan;
   double *loss;
   float rscale;
+  unsigned *rmax;
 };
 
 constexpr int kThreads = 256;
@@ -199,6 +200,7 @@ __global__ void __launch_bounds__(kIThreads) k_interp(InterpDev a) {
   }
   if constexpr (MIX) {
     double my_loss = 0.0;
+    float my_max = 0.f;
 #pragma unroll
     for (int i = 0; i < kPts; ++i) {
       const int q = tid + i * kIThreads;
@@ -210,19 +212,33 @@ __global__ void __launch_bounds__(kIThreads) k_interp(InterpDev a) {
         const float wt = a.w ? a.w[orig] : 1.f;
         my_loss += (double)wt * ((double)df.x * df.x + (double)df.y * df.y);
         const float sw = a.rscale * wt;
-        a.r_plan[(size_t)(wi.y + q) * gridDim.y + grp] = make_float2(sw * df.x, sw * df.y);
+        const float2 rv = make_float2(sw * df.x, sw * df.y);
+        my_max = fmaxf(my_max, fmaxf(fabsf(rv.x), fabsf(rv.y)));
+        a.r_plan[(size_t)(wi.y + q) * gridDim.y + grp] = rv;
       } else {
         a.y[(size_t)grp * a.M + orig] = acc[i];
       }
     }
     if constexpr (DC) {
       __shared__ double part[kIThreads / 64];
-      for (int off = 32; off > 0; off >>= 1) my_loss += __shfl_down(my_loss, off, 64);
-      if ((tid & 63) == 0) part[tid >> 6] = my_loss;
+      __shared__ float pmax[kIThreads / 64];
+      for (int off = 32; off > 0; off >>= 1) {
+        my_loss += __shfl_down(my_loss, off, 64);
+        my_max = fmaxf(my_max, __shfl_xor(my_max, off, 64));
+      }
+      if ((tid & 63) == 0) {
+        part[tid >> 6] = my_loss;
+        pmax[tid >> 6] = my_max;
+      }
       __syncthreads();
       if (tid == 0) {
         double s = 0.0;
-        for (int i = 0; i < kIThreads / 64; ++i) s += part[i];
+        float mx = 0.f;
+        for (int i = 0; i < kIThreads / 64; ++i) {
+          s += part[i];
+          mx = fmaxf(mx, pmax[i]);
+        }
+        if (a.rmax) atomicMax(a.rmax, __float_as_uint(mx));
         atomicAdd(a.loss, s);
       }
     }
@@ -940,11 +956,13 @@ hipError_t launch_interp(const sdn_plan_s &p, const InterpArgs &a, hipStream_t s
   d.r_plan = a.r_plan;
   d.loss = a.loss;
   d.rscale = a.rscale;
+  d.rmax = a.dc ? a.rmax : nullptr;
   const bool mix = a.V != nullptr;
   const bool dc = a.dc != 0;
   if (dc && (!mix || a.r_plan == nullptr || a.loss == nullptr)) return hipErrorInvalidValue;
   const size_t lds = interp_lds_bytes(p);
   if (lds > max_lds_bytes()) return hipErrorInvalidValue;
+  if (d.rmax) hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, d.rmax, 1);
   dim3 grd((unsigned)p.nwork, (unsigned)a.groups);
   switch (p.W) {
     case 4: return interp_launch<4>(d, mix, dc, grd, lds, st);
@@ -1032,11 +1050,16 @@ hipError_t launch_spread(const sdn_plan_s &p, const SpreadArgs &a, hipStream_t s
   dim3 grd((unsigned)p.nsitems, (unsigned)a.groups);
   hipError_t e;
   if (mix && spread_engine_for(p, a.K, a.groups)) {
-    // value scale: the largest component of the residuals and of V
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, p.absmax, 2);
-    const size_t nsrc = (size_t)a.groups * p.M;
-    const unsigned nblk = (unsigned)std::min<size_t>(2048, (nsrc + 1023) / 1024);
-    hipLaunchKernelGGL(k_absmax, dim3(nblk), dim3(256), 0, st, a.src, nsrc, p.absmax);
+    // value scale: the largest component of the residuals (unless the
+    // interpolation that produced them recorded it) and of V
+    if (a.src_max_ready) {
+      hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, p.absmax + 1, 1);
+    } else {
+      hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, p.absmax, 2);
+      const size_t nsrc = (size_t)a.groups * p.M;
+      const unsigned nblk = (unsigned)std::min<size_t>(2048, (nsrc + 1023) / 1024);
+      hipLaunchKernelGGL(k_absmax, dim3(nblk), dim3(256), 0, st, a.src, nsrc, p.absmax);
+    }
     hipLaunchKernelGGL(k_absmax, dim3(1), dim3(256), 0, st, a.V, (size_t)p.T * a.K,
                        p.absmax + 1);
     e = hipGetLastError();

@@ -215,6 +215,8 @@ struct InterpArgs {
   const float *w;   // [M] user order, or null
   float2 *r_plan;   // [M][groups] plan order, a point's coils side by side
   double *loss;
+  unsigned *rmax;   // DC mode, or null: set to the largest |component| of r
+                    // (as float bits), for the spreading that follows
 };
 hipError_t launch_interp(const sdn_plan_s &p, const InterpArgs &a, hipStream_t st);
 size_t interp_lds_bytes(const sdn_plan_s &p);
@@ -233,6 +235,8 @@ struct SpreadArgs {
   const float2 *src;  // user order: [rows][M]; plan order (mix mode only):
                       // [M][groups], a point's coils side by side
   bool src_plan_order;
+  bool src_max_ready; // the plan's scale word 0 already holds the largest |component|
+                      // of src (written by the interpolation that produced it)
 };
 hipError_t launch_spread(const sdn_plan_s &p, const SpreadArgs &a, hipStream_t st);
 // True when a spreading call with K channels per group and `groups` groups

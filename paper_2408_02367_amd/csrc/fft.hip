@@ -9,7 +9,8 @@
 //   z pass: reads the N_z nonzero planes, writes the whole grid.
 // Adjoint (fine grid -> image), the same passes reversed with the output
 // pruned to the image modes; the last x pass is fused with the crop,
-// deapodisation, conj(S_c) multiply and the sum over coils.
+// deapodisation, conj(S_c) multiply and the sum over coils (for coil counts
+// dividing 16; otherwise the crop and the coil sum are two kernels).
 #include <algorithm>
 
 #include "fft_lds.h"

@@ -10,12 +10,14 @@
 //   channel, stages the tile plus its W-1 halo in LDS with coalesced loads,
 //   then every lane interpolates its points from LDS and accumulates the
 //   subspace mix y_b = sum_k V[t][k] u_{b,k} (running sums behind the tile);
-// * spreading: a wave owns one 8 x 8 x 8 block and gathers the
-//   contributions of the points whose support touches it (the plan's list
-//   for the block) into registers, then writes the block once - no atomics,
-//   no separate clear of the grid (every block is written exactly once) and
-//   a fixed summation order.  Crowded blocks are split into several items
-//   whose partial blocks a small reduction sums.
+// * spreading: an 8 x 8 x 8 block gathers the contributions of the points
+//   whose support touches it (the plan's list for the block), either on the
+//   matrix cores (a workgroup of one wave per coil, the block's sum as a
+//   product over the list entries) or by a vector-ALU walk into registers,
+//   then writes the block once - no atomics, no separate clear of the grid
+//   (every block is written exactly once) and a fixed summation order.
+//   Crowded blocks are split into several items whose partial blocks a
+//   small reduction sums.
 #include <algorithm>
 
 #include "fft_lds.h"

@@ -178,3 +178,23 @@ def test_argument_errors(case):
     p.close()
     with pytest.raises(sdn.SdnError):
         sdn.mrf_forward(p, x, s, [0], V)
+
+
+@pytest.mark.parametrize("B", [8, 16, 6])
+def test_adjoint_coil_counts_of_the_fused_inverse_x_pass(B):
+    """8 and 16 coils take the inverse x pass fused with the coil sum (2 and 1
+    image rows per workgroup), 6 the separate crop and sum; all equal the
+    plain per-coil/per-channel path and the FP64 oracle."""
+    shape, K, T = (12, 14, 16), 2, 3
+    traj, frame = wl.spiral_trajectory(T, 4, 200)
+    p = sdn.Plan(to_gpu(traj), shape, frame_of_point=to_gpu(frame), T=T)
+    smaps = wl.coil_maps(shape, B, 31)
+    V = wl.subspace_basis(T, K, 31)
+    ci = np.arange(B, dtype=np.int32)[::-1].copy()
+    r = wl.random_kspace((B, traj.shape[0]), 32)
+    ab = host(sdn.mrf_adjoint(p, c64(r), c64(smaps), ci, c64(V)))
+    ap = host(sdn.mrf_adjoint(p, c64(r), c64(smaps), ci, c64(V), plain=True))
+    assert rel(ab, ap) < 1e-6
+    ref = omrf.adjoint(omrf.Nufft(shape, "gridding"), r, smaps, ci, V, frame,
+                       traj.astype(np.float64), K)
+    assert rel(ab, ref) < 2e-5

@@ -30,7 +30,15 @@ WORKLOADS = {
     "paper": "paper-shaped step: 200^3 x K=5 subspace image, 1-of-8 coil minibatch (one coil "
              "per stochastic step), T=880 frames x 28 spiral arms x 876 samples (M=21.59M), "
              "KB W=6, sigma=2 (400^3 grid): DC gradient",
+    "small": "latency-bound step: 32^3 x K=5 subspace image, 4-of-8 coil minibatch, T=8 frames "
+             "x 1 spiral arm x 1024 samples (M=8192), KB W=6, sigma=2 (64^3 grid): batched DC "
+             "gradient",
+    "ragged": "ragged volumes in one group call: 128^3 (T=512), 160^3 (T=1000) and "
+              "160x192x192 (T=1440), each 8 spiral arms x 1200 samples per frame with its own "
+              "trajectory and V, K=5, 4-of-32 coils: batched DC gradient",
 }
+# member workloads of the ragged group
+RAGGED = ["c3r128", "c4", "c3r192"]
 
 
 def _args():
@@ -160,38 +168,24 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    _log("drawing the synthetic workload")
-    w = wl.make(a.workload)
-    shape, K, B = w["shape"], w["K"], w["B"]
-    M = w["traj"].shape[0]
-    x_true = w["x"]
-    # the point of evaluation: 10% RMS smooth perturbation of the truth
-    pert = wl.phantom(shape, K, w["seed"] + 100)
-    pert *= 0.1 * np.sqrt(np.mean(np.abs(x_true) ** 2) / np.mean(np.abs(pert) ** 2))
-    x_np = (x_true + pert).astype(np.complex64)
-
-    _log("building the plan")
-    plan = sdn.Plan(torch.from_numpy(w["traj"]).to(dev), shape,
-                    frame_of_point=torch.from_numpy(w["frame"]).to(dev), T=w["T"],
-                    spread_engine=a.spread_engine)
-    info = plan.info()
-    smaps = torch.from_numpy(w["smaps"]).to(dev)
-    V = torch.from_numpy(w["V"]).to(dev)
-    ci = w["coil_idx"]
-    xt = torch.from_numpy(x_true).to(dev)
-    x = torch.from_numpy(x_np).to(dev)
-    # simulated measurements of the minibatch coils: A x_true + 1% noise
-    y_clean = sdn.mrf_forward(plan, xt, smaps, ci, V)
-    torch.cuda.synchronize()
-    rms = torch.sqrt(torch.mean(torch.abs(y_clean) ** 2, dim=1)).cpu().numpy()
-    noise = wl.complex_noise((B, M), 0.01, rms, w["seed"])
-    d = (y_clean + torch.from_numpy(noise).to(dev)).contiguous()
-    del y_clean, xt
-    grad = torch.empty_like(x)
-    loss = torch.empty(1, dtype=torch.float64, device=dev)
+    names = RAGGED if a.workload == "ragged" else [a.workload]
+    vols = []
+    for name in names:
+        _log(f"drawing the synthetic workload {name}")
+        vols.append(_volume(name, a, dev, torch, sdn, wl))
+    K, B = vols[0]["K"], vols[0]["B"]
+    P = B * K
+    group = sdn.PlanGroup([v["plan"] for v in vols]) if len(vols) > 1 else None
 
     def step():
-        sdn.mrf_dc_grad(plan, x, smaps, ci, V, d, grad=grad, loss=loss)
+        if group is None:
+            v = vols[0]
+            sdn.mrf_dc_grad(v["plan"], v["x"], v["smaps"], v["ci"], v["V"], v["d"],
+                            grad=v["grad"], loss=v["loss"])
+        else:
+            group.mrf_dc_grad([v["x"] for v in vols], [v["smaps"] for v in vols],
+                              [v["ci"] for v in vols], [v["V"] for v in vols],
+                              [v["d"] for v in vols])
 
     _log("warmup")
     for _ in range(a.warmup):
@@ -226,28 +220,35 @@ def main():
     t1 = time.perf_counter()
     per_step = np.array([e0.elapsed_time(e1) for e0, e1 in ev])
     ms_step = (t1 - t0) * 1e3 / a.steps
-    P = B * K
-    value = M * P / (ms_step * 1e-3)
+    M_all = sum(v["M"] for v in vols)
+    value = M_all * P / (ms_step * 1e-3)
     # per-stage breakdown: eager steps with HIP events around every launch
     _log(f"timed: {ms_step:.3f} ms/step; stage breakdown")
-    plan.profile(True)
-    plan.profile_read(reset=True)
+    for v in vols:
+        v["plan"].profile(True)
+        v["plan"].profile_read(reset=True)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     for _ in range(a.steps):
         step()
     torch.cuda.synchronize()
     eager_ms = (time.perf_counter() - t2) * 1e3 / a.steps
-    stages = plan.profile_read(reset=True)
-    plan.profile(False)
+    stages = {}
+    for v in vols:
+        for st, (ms, n) in v["plan"].profile_read(reset=True).items():
+            m0, n0 = stages.get(st, (0.0, 0))
+            stages[st] = (m0 + ms, n0 + n)
+        v["plan"].profile(False)
 
-    # the plain per-coil/per-channel path on the same plan and data
-    yp = torch.empty_like(d)
-    xo = torch.empty_like(x)
+    # the plain per-coil/per-channel path on the same plans and data
+    for v in vols:
+        v["yp"] = torch.empty_like(v["d"])
+        v["xo"] = torch.empty_like(v["x"])
 
     def plain_step():
-        sdn.mrf_forward(plan, x, smaps, ci, V, out=yp, plain=True)
-        sdn.mrf_adjoint(plan, d, smaps, ci, V, out=xo, plain=True)
+        for v in vols:
+            sdn.mrf_forward(v["plan"], v["x"], v["smaps"], v["ci"], v["V"], out=v["yp"], plain=True)
+            sdn.mrf_adjoint(v["plan"], v["d"], v["smaps"], v["ci"], v["V"], out=v["xo"], plain=True)
 
     plain_ms, plain_stages = None, None
     if a.plain_steps > 0:
@@ -260,11 +261,15 @@ def main():
         torch.cuda.synchronize()
         plain_ms = (time.perf_counter() - t0) * 1e3 / a.plain_steps
         # stage breakdown of one more plain step (not part of the timing above)
-        plan.profile(True)
-        plan.profile_read(reset=True)
+        for v in vols:
+            v["plan"].profile(True)
+            v["plan"].profile_read(reset=True)
         plain_step()
-        plain_stages = {s: round(ms, 3) for s, (ms, n) in plan.profile_read(reset=True).items()}
-        plan.profile(False)
+        plain_stages = {}
+        for v in vols:
+            for st, (ms, n) in v["plan"].profile_read(reset=True).items():
+                plain_stages[st] = round(plain_stages.get(st, 0.0) + ms, 3)
+            v["plan"].profile(False)
     if a.calib_copy_mb > 0:
         n = a.calib_copy_mb * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device=dev)
@@ -273,56 +278,78 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    geo = dict(P=P, B=B, K=K, M=M, Nz=shape[0], Ny=shape[1], Nx=shape[2],
-               nfz=info["fine"][0], nfy=info["fine"][1], nfx=info["fine"][2])
-    sb = stage_bytes(geo)
-    sf = stage_flops(geo, info["W"])
-    # on-chip bytes of the interpolation: every (point, channel) reads its
-    # W^3 cells (8 B each) from the LDS tile
-    sl = {"interp": 8 * info["W"] ** 3 * M * P}
+    # algorithmic bytes and flops of one step per stage, summed over volumes;
+    # a single volume's step launches each stage once (or once per coil chunk,
+    # whose bytes add up to the same total)
+    sb, sf, sl = {}, {}, {}
+    W = vols[0]["info"]["W"]
+    for v in vols:
+        info, shape = v["info"], v["shape"]
+        geo = dict(P=P, B=B, K=K, M=v["M"], Nz=shape[0], Ny=shape[1], Nx=shape[2],
+                   nfz=info["fine"][0], nfy=info["fine"][1], nfx=info["fine"][2])
+        for dct, part in ((sb, stage_bytes(geo)), (sf, stage_flops(geo, W)),
+                          # on-chip bytes of the interpolation: every (point,
+                          # channel) reads its W^3 cells (8 B each) from LDS
+                          (sl, {"interp": 8 * W ** 3 * v["M"] * P})):
+            for st, val in part.items():
+                dct[st] = dct.get(st, 0) + val
     per_stage = {}
-    for s, (ms, n) in stages.items():
+    for st, (ms, n) in stages.items():
         avg = ms / n
-        per_stage[s] = {"ms_per_step": round(ms / a.steps, 4), "launches": n,
-                        "avg_launch_ms": round(avg, 4)}
-        if s in sb:
-            per_stage[s]["algo_GBps"] = round(sb[s] / (avg * 1e-3) / 1e9, 1)
-            per_stage[s]["hbm_frac"] = round(sb[s] / (avg * 1e-3) / 8.0e12, 4)
-        if s in sf:
-            per_stage[s]["TFLOPs"] = round(sf[s] / (avg * 1e-3) / 1e12, 2)
+        t_step = ms / a.steps * 1e-3
+        per_stage[st] = {"ms_per_step": round(ms / a.steps, 4), "launches": n,
+                         "avg_launch_ms": round(avg, 4)}
+        if st in sb:
+            per_stage[st]["algo_GBps"] = round(sb[st] / t_step / 1e9, 1)
+            per_stage[st]["hbm_frac"] = round(sb[st] / t_step / 8.0e12, 4)
+        if st in sf:
+            per_stage[st]["TFLOPs"] = round(sf[st] / t_step / 1e12, 2)
             # against the FP32 vector peak (157.3 TFLOP/s with packed FP32)
-            per_stage[s]["fp32_vector_frac"] = round(sf[s] / (avg * 1e-3) / 157.3e12, 4)
-        if s in sl:
-            per_stage[s]["lds_read_TBps"] = round(sl[s] / (avg * 1e-3) / 1e12, 1)
-    dom = max((s for s in stages if s in sb), key=lambda s: stages[s][0])
+            per_stage[st]["fp32_vector_frac"] = round(sf[st] / t_step / 157.3e12, 4)
+        if st in sl:
+            per_stage[st]["lds_read_TBps"] = round(sl[st] / t_step / 1e12, 1)
+    dom = max((st for st in stages if st in sb), key=lambda st: stages[st][0])
+    launches_per_step = stages[dom][1] / a.steps
     dom_avg_s = stages[dom][0] / stages[dom][1] * 1e-3
-    if dom == "spread" and info["spread_engine"] == "matrix":
+    dom_step_s = stages[dom][0] / a.steps * 1e-3
+    engine = vols[0]["info"]["spread_engine"] if B > 1 else "gather"
+    if dom == "spread" and engine == "matrix":
         # the spreading sum runs on the matrix cores in fp16 (operands split
         # into hi + lo parts, three products, FP32 accumulation): dense fp16
         # MFMA peak 2.5 PFLOP/s; achieved counts the algorithmic flops
-        achieved = sf[dom] / dom_avg_s / 1e12
-        blocks = info["nvisit"] * B                    # (entry, coil) block products
-        executed = blocks * 64 * 16 * K * 3 * 2        # 64 x 16K outputs per entry, 3 products
+        achieved = sf[dom] / dom_step_s / 1e12
+        blocks = sum(v["info"]["nvisit"] for v in vols) * B   # (entry, coil) block products
+        executed = blocks * 64 * 16 * K * 3 * 2               # 64 x 16K outputs per entry, 3 products
         roofline = {"kernel": dom, "bound": "mfma", "achieved": round(achieved, 2), "peak": 2500.0,
                     "unit": "TFLOP/s", "frac": round(achieved / 2500.0, 4),
-                    "algo_flops_per_launch": sf[dom], "algo_bytes_per_launch": sb[dom],
-                    "algo_hbm_GBps": round(sb[dom] / dom_avg_s / 1e9, 1),
-                    "mfma_executed_TFLOPs": round(executed / dom_avg_s / 1e12, 1)}
+                    "algo_flops_per_launch": sf[dom] / launches_per_step,
+                    "algo_bytes_per_launch": sb[dom] / launches_per_step,
+                    "algo_hbm_GBps": round(sb[dom] / dom_step_s / 1e9, 1),
+                    "mfma_executed_TFLOPs": round(executed / dom_step_s / 1e12, 1)}
     elif dom in sf:
         # arithmetic intensity above the FP32 ridge (157.3 TFLOP/s / 8 TB/s)
-        achieved = sf[dom] / dom_avg_s / 1e12
+        achieved = sf[dom] / dom_step_s / 1e12
         roofline = {"kernel": dom, "bound": "alu", "achieved": round(achieved, 2), "peak": 157.3,
                     "unit": "TFLOP/s", "frac": round(achieved / 157.3, 4),
-                    "algo_flops_per_launch": sf[dom], "algo_bytes_per_launch": sb[dom],
-                    "algo_hbm_GBps": round(sb[dom] / dom_avg_s / 1e9, 1)}
+                    "algo_flops_per_launch": sf[dom] / launches_per_step,
+                    "algo_bytes_per_launch": sb[dom] / launches_per_step,
+                    "algo_hbm_GBps": round(sb[dom] / dom_step_s / 1e9, 1)}
     else:
-        achieved = sb[dom] / dom_avg_s / 1e9
+        achieved = sb[dom] / dom_step_s / 1e9
         roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0,
                     "unit": "GB/s", "frac": round(achieved / 8000.0, 4),
-                    "algo_bytes_per_launch": sb[dom]}
+                    "algo_bytes_per_launch": sb[dom] / launches_per_step}
     roofline["traffic"] = measured_traffic(dom, a.workload)
     roofline["avg_launch_ms"] = round(dom_avg_s * 1e3, 4)
 
+    v0 = vols[0]
+    config = {"workload": WORKLOADS[a.workload], "name": a.workload, "spread_engine": engine,
+              "K": K, "B": B, "W": v0["info"]["W"], "sigma": v0["info"]["sigma"]}
+    if len(vols) == 1:
+        config.update({"shape": list(v0["shape"]), "C": v0["C"], "M": v0["M"], "T": v0["T"]})
+    else:
+        config["volumes"] = [{"shape": list(v["shape"]), "C": v["C"], "M": v["M"], "T": v["T"]}
+                             for v in vols]
     out = {
         "metric": "NUFFT fwd+adj nonuniform pts*ch/s (minibatch DC gradient)",
         "value": round(value, 1),
@@ -339,23 +366,52 @@ def main():
         "vs_baseline": None,
         "dtype": "fp32",
         "data": "synthetic",
-        "config": {"workload": WORKLOADS[a.workload], "name": a.workload,
-                   "spread_engine": info["spread_engine"],
-                   "shape": list(shape), "K": K, "B": B, "C": w["C"], "M": M, "T": w["T"],
-                   "W": info["W"], "sigma": info["sigma"]},
+        "config": config,
         "plain_ms_per_step": round(plain_ms, 3) if plain_ms else None,
         "speedup_vs_plain": round(plain_ms / ms_step, 3) if plain_ms else None,
         "plain_stages_ms": plain_stages,
         "stages": per_stage,
         "roofline": roofline,
         "torch_peak_mem_GB": round(torch.cuda.max_memory_allocated() / 1e9, 2),
-        "plan_workspace_GB": round(plan.workspace_size(B, K) / 1e9, 2),
+        "plan_workspace_GB": round(sum(v["plan"].workspace_size(B, K) for v in vols) / 1e9, 2),
     }
     _log(f"plain: {plain_ms} ms/step")
     if not a.no_cpu_baseline:
         _log("timing the CPU oracle sample")
+        w = v0["w"]
         out["cpu_baseline"] = cpu_baseline(w, w["x"], w["smaps"], a.cpu_sample)
     print(json.dumps(out), flush=True)
+
+
+def _volume(name, a, dev, torch, sdn, wl):
+    """One volume of a workload on the device: plan, images, coil maps, V and
+    simulated measurements d = A x_true + 1% noise of the minibatch coils,
+    with the evaluation point x a 10% RMS smooth perturbation of x_true."""
+    w = wl.make(name)
+    shape, K, B = w["shape"], w["K"], w["B"]
+    M = w["traj"].shape[0]
+    x_true = w["x"]
+    pert = wl.phantom(shape, K, w["seed"] + 100)
+    pert *= 0.1 * np.sqrt(np.mean(np.abs(x_true) ** 2) / np.mean(np.abs(pert) ** 2))
+    x_np = (x_true + pert).astype(np.complex64)
+    _log(f"building the plan of {name}")
+    plan = sdn.Plan(torch.from_numpy(w["traj"]).to(dev), shape,
+                    frame_of_point=torch.from_numpy(w["frame"]).to(dev), T=w["T"],
+                    spread_engine=a.spread_engine)
+    smaps = torch.from_numpy(w["smaps"]).to(dev)
+    V = torch.from_numpy(w["V"]).to(dev)
+    ci = w["coil_idx"]
+    xt = torch.from_numpy(x_true).to(dev)
+    y_clean = sdn.mrf_forward(plan, xt, smaps, ci, V)
+    torch.cuda.synchronize()
+    rms = torch.sqrt(torch.mean(torch.abs(y_clean) ** 2, dim=1)).cpu().numpy()
+    noise = wl.complex_noise((B, M), 0.01, rms, w["seed"])
+    d = (y_clean + torch.from_numpy(noise).to(dev)).contiguous()
+    del y_clean, xt
+    x = torch.from_numpy(x_np).to(dev)
+    return dict(w=w, name=name, shape=shape, K=K, B=B, C=w["C"], M=M, T=w["T"], plan=plan,
+                info=plan.info(), smaps=smaps, V=V, ci=ci, x=x, d=d,
+                grad=torch.empty_like(x), loss=torch.empty(1, dtype=torch.float64, device=dev))
 
 
 if __name__ == "__main__":

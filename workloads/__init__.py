@@ -200,8 +200,12 @@ CONFIGS = {
     # frames, 28 spiral arms per frame at R = 2, 876 samples per arm; one
     # coil per stochastic step as in Alg. 1), K = 5 channels: M = 21.59M
     "paper": dict(shape=(200, 200, 200), K=5, C=8, B=1, T=880, L=28, S=876),
+    # the batched step at the plain-NUFFT geometry (32^3, 64^3 grid, 8192
+    # points): the launch-latency-bound case
+    "small": dict(shape=(32, 32, 32), K=5, C=8, B=4, T=8, L=1, S=1024),
 }
-SEEDS = {"c1": 1, "c2": 2, "c3": 3, "c3r128": 31, "c3r192": 32, "c4": 4, "c5": 5, "paper": 6}
+SEEDS = {"c1": 1, "c2": 2, "c3": 3, "c3r128": 31, "c3r192": 32, "c4": 4, "c5": 5, "paper": 6,
+         "small": 7}
 
 
 def make(name, with_images=True, minibatch_maps=False):

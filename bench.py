@@ -55,6 +55,9 @@ def _args():
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="c4",
                     help="c4 (the default, the headline configuration) or the paper-shaped step")
     ap.add_argument("--spread-engine", choices=["auto", "gather", "matrix"], default="auto")
+    ap.add_argument("--autotune", action="store_true",
+                    help="build each plan with the options sdn_autotune finds fastest "
+                         "(tile, points per item, spreading engine); untimed")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -344,7 +347,8 @@ def main():
 
     v0 = vols[0]
     config = {"workload": WORKLOADS[a.workload], "name": a.workload, "spread_engine": engine,
-              "K": K, "B": B, "W": v0["info"]["W"], "sigma": v0["info"]["sigma"]}
+              "K": K, "B": B, "W": v0["info"]["W"], "sigma": v0["info"]["sigma"],
+              "autotuned": bool(a.autotune), "tile": list(v0["info"]["tile"])}
     if len(vols) == 1:
         config.update({"shape": list(v0["shape"]), "C": v0["C"], "M": v0["M"], "T": v0["T"]})
     else:
@@ -394,10 +398,15 @@ def _volume(name, a, dev, torch, sdn, wl):
     pert = wl.phantom(shape, K, w["seed"] + 100)
     pert *= 0.1 * np.sqrt(np.mean(np.abs(x_true) ** 2) / np.mean(np.abs(pert) ** 2))
     x_np = (x_true + pert).astype(np.complex64)
+    opts = {"spread_engine": a.spread_engine}
+    if a.autotune:
+        _log(f"autotuning the plan of {name}")
+        tuned = sdn.autotune(torch.from_numpy(w["traj"]).to(dev), shape, B, K,
+                             frame_of_point=torch.from_numpy(w["frame"]).to(dev), T=w["T"])
+        opts = {k: tuned[k] for k in sdn.TUNED_KEYS}
     _log(f"building the plan of {name}")
     plan = sdn.Plan(torch.from_numpy(w["traj"]).to(dev), shape,
-                    frame_of_point=torch.from_numpy(w["frame"]).to(dev), T=w["T"],
-                    spread_engine=a.spread_engine)
+                    frame_of_point=torch.from_numpy(w["frame"]).to(dev), T=w["T"], **opts)
     smaps = torch.from_numpy(w["smaps"]).to(dev)
     V = torch.from_numpy(w["V"]).to(dev)
     ci = w["coil_idx"]

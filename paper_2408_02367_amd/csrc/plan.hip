@@ -594,16 +594,23 @@ sdn_status sdn_plan_create(sdn_plan *out, const int64_t shape[3], const float *t
     if (s == SDN_OK) {
       std::vector<int4> sitems, splits;
       int64_t acc = 0, slot = 0;
+      // entries per item: kSpreadCap, or fewer when the whole plan has few
+      // entries, so that a small, centre-heavy trajectory still spreads over
+      // enough workgroups (a multiple of the 32-entry batches, >= 512)
+      int64_t total = 0;
+      for (int b = 0; b < nsb; ++b) total += scount[b];
+      const int cap = (int)std::min<int64_t>(kSpreadCap,
+                                             std::max<int64_t>(512, total / 2048 / 32 * 32));
       for (int b = 0; b < nsb; ++b) {
         const int c = scount[b];
-        const int nch = std::max(1, (c + kSpreadCap - 1) / kSpreadCap);
+        const int nch = std::max(1, (c + cap - 1) / cap);
         if (nch == 1) {
           sitems.push_back(make_int4(b, (int)acc, c, -1));
         } else {
           splits.push_back(make_int4(b, (int)slot, nch, 0));
           for (int q = 0; q < nch; ++q)
-            sitems.push_back(make_int4(b, (int)acc + q * kSpreadCap,
-                                       std::min(kSpreadCap, c - q * kSpreadCap), (int)slot++));
+            sitems.push_back(make_int4(b, (int)acc + q * cap, std::min(cap, c - q * cap),
+                                       (int)slot++));
         }
         acc += c;
         if (acc > INT32_MAX - 1024) break;

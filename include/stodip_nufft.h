@@ -65,7 +65,8 @@ typedef struct {
   int tile;                /* tile edge in fine cells, 4..32 on every axis;
                               0 = library choice (16 x 16 x 8)                      */
   int max_points_per_item; /* cap on points per interpolation work item, <= 2048;
-                              0 = library choice (2048)                              */
+                              0 = library choice (2048; a power of two down to
+                              512 for plans of under a million points)            */
   size_t workspace_budget; /* bytes of fine-grid workspace; 0 = unlimited.  Calls
                               whose coil minibatch does not fit run coil-chunked.   */
   int spread_engine;       /* type-1 spreading kernel: SDN_SPREAD_AUTO (default:

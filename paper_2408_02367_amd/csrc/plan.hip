@@ -408,7 +408,12 @@ sdn_status sdn_plan_create(sdn_plan *out, const int64_t shape[3], const float *t
   if (o.spread_engine < SDN_SPREAD_AUTO || o.spread_engine > SDN_SPREAD_MATRIX)
     return delete p, fail(SDN_E_INVALID, "sdn_plan_create: unknown spread_engine");
   p->spread_engine = o.spread_engine;
-  p->max_points_per_item = o.max_points_per_item > 0 ? o.max_points_per_item : kItemCap;
+  // library choice: kItemCap points per interpolation item, fewer (a power of
+  // two, >= 512) for plans of under a million points so that they still
+  // spread over enough workgroups
+  int auto_cap = 512;
+  while (auto_cap < kItemCap && (int64_t)auto_cap * 2 * 512 <= M) auto_cap *= 2;
+  p->max_points_per_item = o.max_points_per_item > 0 ? o.max_points_per_item : auto_cap;
   if (p->max_points_per_item > kItemCap)
     return delete p, fail(SDN_E_INVALID, "sdn_plan_create: max_points_per_item above 2048");
 

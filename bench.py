@@ -55,6 +55,10 @@ def _args():
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="c4",
                     help="c4 (the default, the headline configuration) or the paper-shaped step")
     ap.add_argument("--spread-engine", choices=["auto", "gather", "matrix"], default="auto")
+    ap.add_argument("--extras", action="store_true",
+                    help="also time the calls around the step on the first volume: normal "
+                         "operator and CG iterations over all coils, scaled adjoint, full-coil "
+                         "DC gradient, TV value/gradient, density compensation")
     ap.add_argument("--autotune", action="store_true",
                     help="build each plan with the options sdn_autotune finds fastest "
                          "(tile, points per item, spreading engine); untimed")
@@ -380,11 +384,57 @@ def main():
         "plan_workspace_GB": round(sum(v["plan"].workspace_size(B, K) for v in vols) / 1e9, 2),
     }
     _log(f"plain: {plain_ms} ms/step")
+    if a.extras:
+        _log("timing the calls around the step")
+        out["extras"] = _extras(v0, torch, sdn)
     if not a.no_cpu_baseline:
         _log("timing the CPU oracle sample")
         w = v0["w"]
         out["cpu_baseline"] = cpu_baseline(w, w["x"], w["smaps"], a.cpu_sample)
     print(json.dumps(out), flush=True)
+
+
+def _timed(fn, torch, reps=3):
+    """Milliseconds per call of fn (after one untimed call), HIP events on
+    the current stream."""
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return round(e0.elapsed_time(e1) / reps, 3)
+
+
+def _extras(v, torch, sdn):
+    """Times of the initialisers (all C coils), the full-coil DC gradient, the
+    TV penalty and the density compensation on one volume's plan and data."""
+    plan, x, smaps, V = v["plan"], v["x"], v["smaps"], v["V"]
+    C, M, K = v["C"], v["M"], v["K"]
+    allc = list(range(C))
+    y = sdn.mrf_forward(plan, x, smaps, allc, V)          # data of every coil
+    torch.cuda.synchronize()
+    out = {"coils": C, "channels": K, "points": M}
+    out["normal_op_ms"] = _timed(lambda: sdn.mrf_normal(plan, x, smaps, V), torch)
+    iters = 4
+    t_cg = _timed(lambda: sdn.mrf_cg(plan, y, smaps, V, iterations=iters, K=K), torch, reps=1)
+    t_cg0 = _timed(lambda: sdn.mrf_cg(plan, y, smaps, V, iterations=0, K=K), torch, reps=1)
+    out["cg_ms_per_iteration"] = round((t_cg - t_cg0) / iters, 3)
+    out["cg_setup_ms"] = t_cg0
+    out["scaled_adjoint_ms"] = _timed(lambda: sdn.mrf_scaled_adjoint(plan, y, smaps, V), torch)
+    grad = torch.empty_like(x)
+    loss = torch.empty(1, dtype=torch.float64, device=x.device)
+    out["full_coil_dc_grad_ms"] = _timed(
+        lambda: sdn.mrf_dc_grad(plan, x, smaps, allc, V, y, grad=grad, loss=loss), torch)
+    out["full_coil_pts_ch_per_s"] = round(M * C * K / (out["full_coil_dc_grad_ms"] * 1e-3), 1)
+    out["tv_value_grad_ms"] = _timed(lambda: sdn.tv_grad(plan, x, 1e-3, 1.0), torch)
+    nvox = x.numel() // K
+    # TV: x read, gradient written (8 B each) per voxel and channel
+    out["tv_algo_GBps"] = round(16 * nvox * K / (out["tv_value_grad_ms"] * 1e-3) / 1e9, 1)
+    out["dcf_10_iterations_ms"] = _timed(lambda: sdn.dcf_estimate(plan, 10), torch, reps=1)
+    return out
 
 
 def _volume(name, a, dev, torch, sdn, wl):

@@ -636,11 +636,13 @@ sdn_status sdn_tv_grad(sdn_plan p, const void *x, int K, float eps, float lambda
     return fail(SDN_E_INVALID, "sdn_tv_grad: lambda must be finite and >= 0");
   hipStream_t st = (hipStream_t)stream;
   const int nb = tv_blocks(*p, K);
-  SDN_TRY(ensure_red(p, (size_t)nb));
+  SDN_TRY(ensure_red(p, (size_t)nb + kSumChunks));
   SDN_HIP(launch_tv(*p, (const float2 *)x, K, eps, lambda, (float2 *)grad, accumulate ? 1 : 0,
                     p->red, st),
           "total variation");
-  if (value) SDN_HIP(launch_sum(p->red, nb, (double)lambda, value, st), "total variation sum");
+  if (value)
+    SDN_HIP(launch_sum(p->red, nb, (double)lambda, value, st, p->red + nb),
+            "total variation sum");
   return SDN_OK;
 }
 

@@ -17,12 +17,13 @@ namespace {
 
 constexpr int kRedThreads = 256;
 
-// Sum of one double per thread of a 256-thread block, in a fixed order;
-// the result is valid in thread 0.
+// Sum of one double per thread of a 256-thread block (1D, or 2D with
+// blockDim.x a multiple of 64), in a fixed order; the result is valid in
+// thread 0.
 __device__ double block_sum(double v) {
   __shared__ double part[kRedThreads / 64];
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.y * blockDim.x + threadIdx.x;
   if ((tid & 63) == 0) part[tid >> 6] = v;
   __syncthreads();
   double s = 0.0;
@@ -50,6 +51,17 @@ __global__ void __launch_bounds__(kRedThreads) k_sum(const double *__restrict__ 
   for (int i = threadIdx.x; i < n; i += kRedThreads) s += part[i];
   s = block_sum(s);
   if (threadIdx.x == 0) *out = scale * s;
+}
+
+// First level of a long sum: block b adds the b-th contiguous chunk.
+__global__ void __launch_bounds__(kRedThreads) k_sum_chunks(const double *__restrict__ part,
+                                                            int n, double *__restrict__ out) {
+  const int chunk = (n + gridDim.x - 1) / gridDim.x;
+  const int lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
+  double s = 0.0;
+  for (int i = lo + threadIdx.x; i < hi; i += kRedThreads) s += part[i];
+  s = block_sum(s);
+  if (threadIdx.x == 0) out[blockIdx.x] = s;
 }
 
 __global__ void k_weighted_plan(const int2 *__restrict__ pidx, int M, const float2 *__restrict__ y,
@@ -188,41 +200,44 @@ __device__ __forceinline__ float tv_term(const float2 *xc, int x, int y, int z, 
   }
   const float s = ux.x * ux.x + ux.y * ux.y + uy.x * uy.x + uy.y * uy.y + uz.x * uz.x +
                   uz.y * uz.y + eps2;
-  return sqrtf(s);
+  // 1 / t from the hardware reciprocal square root (s >= eps^2 > 0); the
+  // caller forms t = s / t and the quotients u / t by multiplication
+  return rsqrtf(s);
 }
 
+// Grid (ceil(Nx / 64), ceil(Ny / 4), Nz K), block 64 x 4: the voxel's
+// (x, y, z, k) comes from the indices without per-voxel divisions.
 __global__ void __launch_bounds__(kRedThreads) k_tv(TvDev a) {
-  const size_t gi = (size_t)blockIdx.x * kRedThreads + threadIdx.x;
+  const int x = blockIdx.x * 64 + threadIdx.x;
+  const int y = blockIdx.y * 4 + threadIdx.y;
+  const int k = blockIdx.z / a.nz, z = blockIdx.z - k * a.nz;
   double own = 0.0;
-  if (gi < a.total) {
-    const size_t k = gi / a.nvox;
-    const size_t v = gi - k * a.nvox;
-    const int x = (int)(v % a.nx);
-    const int y = (int)((v / a.nx) % a.ny);
-    const int z = (int)(v / ((size_t)a.nx * a.ny));
-    const float2 *xc = a.x + k * a.nvox;
+  if (x < a.nx && y < a.ny) {
+    const size_t gi = (size_t)k * a.nvox + ((size_t)z * a.ny + y) * a.nx + x;
+    const float2 *xc = a.x + (size_t)k * a.nvox;
     float2 ux, uy, uz;
-    const float t = tv_term(xc, x, y, z, a.nx, a.ny, a.nz, a.eps2, ux, uy, uz);
-    own = (double)t;
+    const float it = tv_term(xc, x, y, z, a.nx, a.ny, a.nz, a.eps2, ux, uy, uz);
+    const float s = ux.x * ux.x + ux.y * ux.y + uy.x * uy.x + uy.y * uy.y + uz.x * uz.x +
+                    uz.y * uz.y + a.eps2;
+    own = (double)(s * it);   // t = s / sqrt(s)
     if (a.grad) {
-      const float it = 1.f / t;
       float gx = -(ux.x + uy.x + uz.x) * it;
       float gy = -(ux.y + uy.y + uz.y) * it;
       float2 px, py, pz;
       if (x > 0) {
-        const float tn = tv_term(xc, x - 1, y, z, a.nx, a.ny, a.nz, a.eps2, px, py, pz);
-        gx += px.x / tn;
-        gy += px.y / tn;
+        const float itn = tv_term(xc, x - 1, y, z, a.nx, a.ny, a.nz, a.eps2, px, py, pz);
+        gx = fmaf(px.x, itn, gx);
+        gy = fmaf(px.y, itn, gy);
       }
       if (y > 0) {
-        const float tn = tv_term(xc, x, y - 1, z, a.nx, a.ny, a.nz, a.eps2, px, py, pz);
-        gx += py.x / tn;
-        gy += py.y / tn;
+        const float itn = tv_term(xc, x, y - 1, z, a.nx, a.ny, a.nz, a.eps2, px, py, pz);
+        gx = fmaf(py.x, itn, gx);
+        gy = fmaf(py.y, itn, gy);
       }
       if (z > 0) {
-        const float tn = tv_term(xc, x, y, z - 1, a.nx, a.ny, a.nz, a.eps2, px, py, pz);
-        gx += pz.x / tn;
-        gy += pz.y / tn;
+        const float itn = tv_term(xc, x, y, z - 1, a.nx, a.ny, a.nz, a.eps2, px, py, pz);
+        gx = fmaf(pz.x, itn, gx);
+        gy = fmaf(pz.y, itn, gy);
       }
       float2 g = make_float2(a.lam * gx, a.lam * gy);
       if (a.accumulate) {
@@ -234,7 +249,8 @@ __global__ void __launch_bounds__(kRedThreads) k_tv(TvDev a) {
     }
   }
   own = block_sum(own);
-  if (threadIdx.x == 0) a.part[blockIdx.x] = own;
+  if (threadIdx.x == 0 && threadIdx.y == 0)
+    a.part[((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = own;
 }
 
 unsigned stream_blocks(size_t n) {
@@ -248,7 +264,14 @@ hipError_t launch_dot(const float2 *a, const float2 *b, size_t n, double *part, 
   return hipGetLastError();
 }
 
-hipError_t launch_sum(const double *part, int n, double scale, double *out, hipStream_t st) {
+hipError_t launch_sum(const double *part, int n, double scale, double *out, hipStream_t st,
+                      double *scratch) {
+  if (scratch && n > 16 * kRedThreads) {
+    hipLaunchKernelGGL(k_sum_chunks, dim3(kSumChunks), dim3(kRedThreads), 0, st, part, n,
+                       scratch);
+    part = scratch;
+    n = kSumChunks;
+  }
   hipLaunchKernelGGL(k_sum, dim3(1), dim3(kRedThreads), 0, st, part, n, scale, out);
   return hipGetLastError();
 }
@@ -293,9 +316,14 @@ hipError_t launch_scale_ratio(float2 *x, size_t n, const double *num, const doub
   return hipGetLastError();
 }
 
+dim3 tv_grid(const sdn_plan_s &p, int K) {
+  return dim3((unsigned)((p.ax[0].N + 63) / 64), (unsigned)((p.ax[1].N + 3) / 4),
+              (unsigned)(K * p.ax[2].N));
+}
+
 int tv_blocks(const sdn_plan_s &p, int K) {
-  const size_t total = (size_t)K * p.ax[0].N * p.ax[1].N * p.ax[2].N;
-  return (int)((total + kRedThreads - 1) / kRedThreads);
+  const dim3 g = tv_grid(p, K);
+  return (int)(g.x * g.y * g.z);
 }
 
 hipError_t launch_tv(const sdn_plan_s &p, const float2 *x, int K, float eps, float lam,
@@ -312,7 +340,8 @@ hipError_t launch_tv(const sdn_plan_s &p, const float2 *x, int K, float eps, flo
   a.eps2 = eps * eps;
   a.lam = lam;
   a.accumulate = accumulate;
-  hipLaunchKernelGGL(k_tv, dim3((unsigned)tv_blocks(p, K)), dim3(kRedThreads), 0, st, a);
+  if ((int64_t)K * p.ax[2].N > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_tv, tv_grid(p, K), dim3(64, 4), 0, st, a);
   return hipGetLastError();
 }
 

@@ -153,8 +153,11 @@ hipError_t launch_fill_zero_f64(double *a, size_t n, hipStream_t st);
 constexpr int kDotBlocks = 1024;
 // part[0 .. kDotBlocks) = partial sums of Re <a, b> over n complex elements
 hipError_t launch_dot(const float2 *a, const float2 *b, size_t n, double *part, hipStream_t st);
-// *out = scale * sum(part[0 .. n))
-hipError_t launch_sum(const double *part, int n, double scale, double *out, hipStream_t st);
+// *out = scale * sum(part[0 .. n)); with scratch (kSumChunks doubles) a long
+// sum runs in two fixed-order levels
+constexpr int kSumChunks = 256;
+hipError_t launch_sum(const double *part, int n, double scale, double *out, hipStream_t st,
+                      double *scratch = nullptr);
 // out[j][g] = scale w[orig(j)] y[g][orig(j)], plan order, for g < groups
 hipError_t launch_weighted_plan(const sdn_plan_s &p, const float2 *y, int groups, const float *w,
                                 float scale, float2 *out, hipStream_t st);

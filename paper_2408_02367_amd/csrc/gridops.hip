@@ -83,9 +83,10 @@ constexpr int kIThreads = 512;                // interpolation workgroup
 // output y_b = sum_k V[t][k] u_k (+ DC epilogue), the running sums kept in
 // registers by the thread that owns the point.  Otherwise a group is K independent channels
 // with outputs y_{gK+k} = u_k.  The plan orders the points of a tile so
-// that every 16 consecutive points start at tile cells of distinct residues
-// mod 16; each 16-lane group's 8-byte LDS reads then hit distinct banks at
-// every one of the W^3 offsets.
+// that every 32 consecutive points start at tile cells of distinct residues
+// mod 32; gfx950 serves an 8-byte LDS read to 32 lanes at a time from 64
+// banks, so each half-wave's reads hit distinct banks at every one of the
+// W^3 offsets.
 template <int W, bool MIX, bool DC, bool BUF>
 __global__ void __launch_bounds__(kIThreads) k_interp(InterpDev a) {
   extern __shared__ float2 tile[];
@@ -158,8 +159,13 @@ __global__ void __launch_bounds__(kIThreads) k_interp(InterpDev a) {
         wz[c] = row(2 * W + c);
       }
       // half a kernel plane at a time: its cells are read into registers
-      // first, so those reads are in flight together
+      // first, so those reads are in flight together.  Each cell is its own
+      // 8-byte read: left alone, the compiler pairs neighbouring cells into
+      // ds_read2_b64, whose two halves then meet bank conflicts whenever the
+      // row starts at an odd cell (about 1.2x slower interpolation here).
+      // Volatile LDS loads are never merged.
       static_assert(W % 2 == 0, "planes are read in halves");
+      typedef const volatile __attribute__((address_space(3))) unsigned long long lds_cell;
       float ur = 0.f, ui = 0.f;
       const float2 *base = tile + (lz * PY + ly) * PX + lx;
 #pragma unroll
@@ -171,7 +177,10 @@ __global__ void __launch_bounds__(kIThreads) k_interp(InterpDev a) {
 #pragma unroll
           for (int ay = 0; ay < W / 2; ++ay)
 #pragma unroll
-            for (int c = 0; c < W; ++c) v[ay][c] = base[(az * PY + hh * (W / 2) + ay) * PX + c];
+            for (int c = 0; c < W; ++c) {
+              const unsigned long long u = *(lds_cell *)(&base[(az * PY + hh * (W / 2) + ay) * PX + c]);
+              v[ay][c] = make_float2(__uint_as_float((unsigned)u), __uint_as_float((unsigned)(u >> 32)));
+            }
 #pragma unroll
           for (int ay = 0; ay < W / 2; ++ay) {
             float tr = 0.f, ti = 0.f;

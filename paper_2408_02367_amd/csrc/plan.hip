@@ -39,8 +39,9 @@ struct FoldGeom {
 
 // Residue classes of a point's first tile cell in the interpolation
 // kernel's LDS copy of the tile (pitches bx + W - 1 and by + W - 1, 8-byte
-// cells): 16 consecutive cells cover the 32 four-byte LDS banks once.
-constexpr int kBankClasses = 16;
+// cells).  gfx950 serves an 8-byte LDS read to 32 lanes at a time from 64
+// four-byte banks, so 32 consecutive cells cover the banks once.
+constexpr int kBankClasses = 32;
 
 // One thread per point.  Fine coordinate s = k nf / (2 pi) in FP64; the W
 // nodes of the point are l0 .. l0+W-1 with l0 = floor(s - W/2) + 1 (the

@@ -83,10 +83,11 @@ constexpr int kIThreads = 512;                // interpolation workgroup
 // output y_b = sum_k V[t][k] u_k (+ DC epilogue), the running sums kept in
 // registers by the thread that owns the point.  Otherwise a group is K independent channels
 // with outputs y_{gK+k} = u_k.  The plan orders the points of a tile so
-// that every 32 consecutive points start at tile cells of distinct residues
-// mod 32; gfx950 serves an 8-byte LDS read to 32 lanes at a time from 64
-// banks, so each half-wave's reads hit distinct banks at every one of the
-// W^3 offsets.
+// that 32 consecutive points mostly start at tile cells of distinct residues
+// mod 32 (or, in crowded tiles, at the same or neighbouring cells); gfx950
+// serves an 8-byte LDS read to 32 lanes at a time from 64 banks, so each
+// half-wave's reads then hit distinct banks, or share a read, at every one
+// of the W^3 offsets.
 template <int W, bool MIX, bool DC, bool BUF>
 __global__ void __launch_bounds__(kIThreads) k_interp(InterpDev a) {
   extern __shared__ float2 tile[];

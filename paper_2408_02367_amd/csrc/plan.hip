@@ -2,10 +2,11 @@
 // fine-grid tiles and sort them tile by tile, then split crowded tiles into
 // work items; build the spreading lists of the 8 x 8 x 8 blocks.
 //
-// Both sorts are stable radix sorts keyed by bin (the points by tile and
-// LDS bank class, the list entries by block and z offset, each in a fixed
-// order within its bin), so a plan, and with it every summation order of
-// the grid kernels, depends on the trajectory only.
+// The sorts are stable radix sorts keyed by bin (the points by tile and
+// LDS bank class, the points of crowded tiles then by first cell, the list
+// entries by block and z offset, each in a fixed order within its bin), so
+// a plan, and with it every summation order of the grid kernels, depends on
+// the trajectory only.
 //
 // The trajectory of an MRF scan is fixed for every data-consistency step of
 // the reconstruction (Sec. 3: thousands of iterations over one scan), so
@@ -42,6 +43,7 @@ struct FoldGeom {
 // cells).  gfx950 serves an 8-byte LDS read to 32 lanes at a time from 64
 // four-byte banks, so 32 consecutive cells cover the banks once.
 constexpr int kBankClasses = 32;
+constexpr int kDenseCellBits = 15;   // tile cells < 2^15 (an LDS tile holds at most 20480)
 
 // One thread per point.  Fine coordinate s = k nf / (2 pi) in FP64; the W
 // nodes of the point are l0 .. l0+W-1 with l0 = floor(s - W/2) + 1 (the
@@ -121,6 +123,62 @@ __global__ void k_place(const unsigned *__restrict__ skey, const int *__restrict
   const int j = order[s];
   rec[dst] = rec_tmp[j];
   pidx[dst] = make_int2(frame ? frame[j] : 0, j);
+}
+
+// Crowded tiles (at least half as many points as the tile has cells) are
+// reordered by first cell after the round-robin: their points pile onto few
+// cells, so classes run out early and the rounds stop lining up with the
+// 32-lane groups, while 32 consecutive points in cell order span at most 32
+// consecutive cells unless they are spread thin (lanes that read one cell
+// share the read).  The points of the crowded tiles form one compact array,
+// tile after tile; dense tile d holds compact entries doff[d] .. doff[d+1]-1
+// and plan positions dstart[d] onward.
+__device__ __forceinline__ int dense_tile_of(const int *doff, int nd, int i) {
+  int lo = 0, hi = nd;   // largest d with doff[d] <= i
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (doff[mid] <= i) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__global__ void k_dense_keys(const float4 *__restrict__ rec, FoldGeom g,
+                             const int *__restrict__ dtile, const int *__restrict__ dstart,
+                             const int *__restrict__ doff, int nd, int md, unsigned *__restrict__ key,
+                             int *__restrict__ val) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= md) return;
+  const int d = dense_tile_of(doff, nd, i);
+  const int j = dstart[d] + (i - doff[d]);
+  const unsigned u = __float_as_uint(rec[j].w);
+  const int lx = (int)(u & 1023u), ly = (int)((u >> 10) & 1023u), lz = (int)((u >> 20) & 1023u);
+  const int b = dtile[d];
+  const int tx = b % g.ntile[0], ty = (b / g.ntile[0]) % g.ntile[1], tz = b / (g.ntile[0] * g.ntile[1]);
+  const int px = g.tile[0] + g.W - 1, py = g.tile[1] + g.W - 1;
+  const int cell = ((lz - tz * g.tile[2]) * py + (ly - ty * g.tile[1])) * px + (lx - tx * g.tile[0]);
+  key[i] = ((unsigned)d << kDenseCellBits) | (unsigned)cell;
+  val[i] = j;
+}
+
+// gather the sorted points (a copy), then write them back to their tiles' ranges
+__global__ void k_dense_gather(const float4 *__restrict__ rec, const int2 *__restrict__ pidx,
+                               const int *__restrict__ src, int md, float4 *__restrict__ rec_out,
+                               int2 *__restrict__ pidx_out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= md) return;
+  rec_out[i] = rec[src[i]];
+  pidx_out[i] = pidx[src[i]];
+}
+
+__global__ void k_dense_put(const float4 *__restrict__ rec_in, const int2 *__restrict__ pidx_in,
+                            const int *__restrict__ dstart, const int *__restrict__ doff, int nd,
+                            int md, float4 *__restrict__ rec, int2 *__restrict__ pidx) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= md) return;
+  const int d = dense_tile_of(doff, nd, i);
+  const int j = dstart[d] + (i - doff[d]);
+  rec[j] = rec_in[i];
+  pidx[j] = pidx_in[i];
 }
 
 // Tiles of one axis touched by the W nodes l0 .. l0+W-1 (mod nf), in order.
@@ -559,6 +617,59 @@ sdn_status sdn_plan_create(sdn_plan *out, const int64_t shape[3], const float *t
       hipLaunchKernelGGL(k_place, grd, dim3(256), 0, st, reinterpret_cast<const unsigned *>(key2),
                          ord, rec_tmp, frame_of_point, m, tstart, ccount, p->rec, p->pidx);
       s = hip_check(hipGetLastError(), "plan placement kernel");
+    }
+    // crowded tiles: reorder by first cell (stable, so ties keep the
+    // round-robin order); skipped when there are too many to key in 32 bits
+    if (s == SDN_OK) {
+      const int ncell = (g.tile[0] + g.W - 1) * (g.tile[1] + g.W - 1) * (g.tile[2] + g.W - 1);
+      std::vector<int> dtile, dstart, doff;
+      int md = 0;
+      for (int b = 0; b < nb; ++b)
+        if (2 * (int64_t)hcount[b] >= ncell && hcount[b] > 1) {
+          dtile.push_back(b);
+          dstart.push_back(hstart[b]);
+          doff.push_back(md);
+          md += hcount[b];
+        }
+      const int nd = (int)dtile.size();
+      if (nd > 0 && nd <= (1 << (32 - kDenseCellBits)) && ncell <= (1 << kDenseCellBits)) {
+        doff.push_back(md);
+        int *ddev = nullptr;
+        int2 *ptmp = nullptr;
+        s = dalloc(&ddev, (size_t)3 * nd + 1, "plan dense tiles");
+        if (s == SDN_OK) s = dalloc(&ptmp, md, "plan dense tiles");
+        int *d_tile = ddev, *d_start = ddev + nd, *d_off = ddev + 2 * nd;
+        if (s == SDN_OK)
+          s = hip_check(hipMemcpyAsync(d_tile, dtile.data(), (size_t)nd * 4, hipMemcpyHostToDevice, st),
+                        "plan dense upload");
+        if (s == SDN_OK)
+          s = hip_check(hipMemcpyAsync(d_start, dstart.data(), (size_t)nd * 4, hipMemcpyHostToDevice, st),
+                        "plan dense upload");
+        if (s == SDN_OK)
+          s = hip_check(hipMemcpyAsync(d_off, doff.data(), (size_t)(nd + 1) * 4, hipMemcpyHostToDevice,
+                                       st),
+                        "plan dense upload");
+        const dim3 gd((md + 255) / 256);
+        if (s == SDN_OK) {
+          // key / key2 / ord_in / ord and rec_tmp are free after the placement
+          hipLaunchKernelGGL(k_dense_keys, gd, dim3(256), 0, st, p->rec, g, d_tile, d_start, d_off,
+                             nd, md, reinterpret_cast<unsigned *>(key), ord_in);
+          s = hip_check(hipGetLastError(), "plan dense key kernel");
+        }
+        if (s == SDN_OK)
+          s = sort_pairs(reinterpret_cast<const unsigned *>(key), reinterpret_cast<unsigned *>(key2),
+                         ord_in, ord, md, key_bits((uint64_t)nd << kDenseCellBits), st);
+        if (s == SDN_OK) {
+          hipLaunchKernelGGL(k_dense_gather, gd, dim3(256), 0, st, p->rec, p->pidx, ord, md, rec_tmp,
+                             ptmp);
+          hipLaunchKernelGGL(k_dense_put, gd, dim3(256), 0, st, rec_tmp, ptmp, d_start, d_off, nd, md,
+                             p->rec, p->pidx);
+          s = hip_check(hipGetLastError(), "plan dense placement kernels");
+        }
+        if (s == SDN_OK) s = hip_check(hipStreamSynchronize(st), "plan sync");
+        hipFree(ddev);
+        hipFree(ptmp);
+      }
     }
     // per-point kernel weights
     if (s == SDN_OK) s = dalloc(&p->wts, (size_t)m * wrec_stride(p->W), "plan weights");

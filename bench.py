@@ -55,6 +55,8 @@ def _args():
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="c4",
                     help="c4 (the default, the headline configuration) or the paper-shaped step")
     ap.add_argument("--spread-engine", choices=["auto", "gather", "matrix"], default="auto")
+    ap.add_argument("--point-order", choices=["auto", "cell"], default="auto",
+                    help="order of the points in an interpolation tile (plan option)")
     ap.add_argument("--extras", action="store_true",
                     help="also time the calls around the step on the first volume: normal "
                          "operator and CG iterations over all coils, scaled adjoint, full-coil "
@@ -352,7 +354,8 @@ def main():
     v0 = vols[0]
     config = {"workload": WORKLOADS[a.workload], "name": a.workload, "spread_engine": engine,
               "K": K, "B": B, "W": v0["info"]["W"], "sigma": v0["info"]["sigma"],
-              "autotuned": bool(a.autotune), "tile": list(v0["info"]["tile"])}
+              "autotuned": bool(a.autotune), "tile": list(v0["info"]["tile"]),
+              "point_order": v0["point_order"]}
     if len(vols) == 1:
         config.update({"shape": list(v0["shape"]), "C": v0["C"], "M": v0["M"], "T": v0["T"]})
     else:
@@ -448,7 +451,7 @@ def _volume(name, a, dev, torch, sdn, wl):
     pert = wl.phantom(shape, K, w["seed"] + 100)
     pert *= 0.1 * np.sqrt(np.mean(np.abs(x_true) ** 2) / np.mean(np.abs(pert) ** 2))
     x_np = (x_true + pert).astype(np.complex64)
-    opts = {"spread_engine": a.spread_engine}
+    opts = {"spread_engine": a.spread_engine, "point_order": a.point_order}
     if a.autotune:
         _log(f"autotuning the plan of {name}")
         tuned = sdn.autotune(torch.from_numpy(w["traj"]).to(dev), shape, B, K,
@@ -469,6 +472,7 @@ def _volume(name, a, dev, torch, sdn, wl):
     del y_clean, xt
     x = torch.from_numpy(x_np).to(dev)
     return dict(w=w, name=name, shape=shape, K=K, B=B, C=w["C"], M=M, T=w["T"], plan=plan,
+                point_order=opts.get("point_order", "auto"),
                 info=plan.info(), smaps=smaps, V=V, ci=ci, x=x, d=d,
                 grad=torch.empty_like(x), loss=torch.empty(1, dtype=torch.float64, device=dev))
 

@@ -77,10 +77,21 @@ typedef struct {
                               with FP32 accumulation; for the subspace calls with
                               >= 2 channels and every fine axis >= 16, else the
                               gather runs; the plain type-1 call always gathers)   */
+  int point_order;         /* order of the points within an interpolation tile:
+                              SDN_ORDER_AUTO (default: round-robin over the 32
+                              LDS residue classes of their first cell, tiles with
+                              at least half as many points as padded cells by
+                              first cell) or SDN_ORDER_CELL (every tile by first
+                              cell: more interpolation bank conflicts, but the
+                              gather spreading of one-coil calls reads its points
+                              more coherently).  Results agree to rounding.       */
 } sdn_opts;
 
 /* Values of sdn_opts.spread_engine. */
 enum { SDN_SPREAD_AUTO = 0, SDN_SPREAD_GATHER = 1, SDN_SPREAD_MATRIX = 2 };
+
+/* Values of sdn_opts.point_order. */
+enum { SDN_ORDER_AUTO = 0, SDN_ORDER_CELL = 1 };
 
 /* Plan facts, for callers and tests. */
 typedef struct {
@@ -310,7 +321,8 @@ SDN_API sdn_status sdn_tv_grad(sdn_plan plan, const void *x, int K, float eps, f
 /*
  * Autotuner: builds candidate plans for one trajectory (interpolation tile
  * edge 16x16x8 / 8 / 16, up to 2048 or 1024 points per work item, gather or
- * matrix-core spreading, all other options from `base`), times three
+ * matrix-core spreading, the gather also with every tile in cell order, all
+ * other options from `base`), times three
  * synthetic DC-gradient steps (coil minibatch B, K channels) of each on
  * `stream`, and returns the fastest option set in *best and its time per
  * step (ms) in *best_ms (may be NULL).  Arguments as sdn_plan_create; the

@@ -52,10 +52,11 @@ class SdnError(RuntimeError):
 class Opts(ctypes.Structure):
     _fields_ = [("W", ctypes.c_int), ("sigma", ctypes.c_double), ("tile", ctypes.c_int),
                 ("max_points_per_item", ctypes.c_int), ("workspace_budget", ctypes.c_size_t),
-                ("spread_engine", ctypes.c_int)]
+                ("spread_engine", ctypes.c_int), ("point_order", ctypes.c_int)]
 
 
 SPREAD_ENGINES = {"auto": 0, "gather": 1, "matrix": 2}
+POINT_ORDERS = {"auto": 0, "cell": 1}
 
 
 class PlanInfo(ctypes.Structure):
@@ -174,7 +175,8 @@ class Plan:
     """
 
     def __init__(self, traj, shape, sigma=2.0, W=6, frame_of_point=None, T=None, tile=0,
-                 max_points_per_item=0, workspace_budget=0, spread_engine="auto"):
+                 max_points_per_item=0, workspace_budget=0, spread_engine="auto",
+                 point_order="auto"):
         L = lib()
         self._h = ctypes.c_void_p()
         traj = torch.as_tensor(traj)
@@ -197,6 +199,7 @@ class Plan:
         o.W, o.sigma, o.tile = int(W), float(sigma), int(tile)
         o.max_points_per_item, o.workspace_budget = int(max_points_per_item), int(workspace_budget)
         o.spread_engine = SPREAD_ENGINES[spread_engine]
+        o.point_order = POINT_ORDERS[point_order]
         sh = (ctypes.c_int64 * 3)(*self.shape)
         with torch.cuda.device(dev):
             _check(L.sdn_plan_create(ctypes.byref(self._h), sh,
@@ -414,7 +417,7 @@ def tv_grad(plan, x, eps, lam=1.0, grad=None, accumulate=False, value=None, want
     return value, grad
 
 
-TUNED_KEYS = ("tile", "max_points_per_item", "spread_engine")
+TUNED_KEYS = ("tile", "max_points_per_item", "spread_engine", "point_order")
 
 
 def tune_key(traj, shape, B, K, W=6, sigma=2.0, frame_of_point=None, device_name=""):
@@ -436,7 +439,7 @@ def autotune(traj, shape, B, K, frame_of_point=None, T=None, W=6, sigma=2.0, cac
     """Plan options that make a DC step fastest for this trajectory.
 
     Returns a dict of Plan keyword arguments (tile, max_points_per_item,
-    spread_engine) plus ``ms`` (time per synthetic step).  With ``cache``
+    spread_engine, point_order) plus ``ms`` (time per synthetic step).  With ``cache``
     (a JSON file path) a result for the same key is reused and new results
     are stored.
     """
@@ -470,8 +473,10 @@ def autotune(traj, shape, B, K, frame_of_point=None, T=None, W=6, sigma=2.0, cac
                                   ctypes.byref(base), ctypes.byref(best), ctypes.byref(ms),
                                   _stream(traj)))
     engines = {v: k for k, v in SPREAD_ENGINES.items()}
+    orders = {v: k for k, v in POINT_ORDERS.items()}
     out = {"tile": best.tile, "max_points_per_item": best.max_points_per_item,
-           "spread_engine": engines[best.spread_engine], "ms": ms.value}
+           "spread_engine": engines[best.spread_engine], "point_order": orders[best.point_order],
+           "ms": ms.value}
     if cache is not None:
         table[key] = out
         tmp = cache + ".tmp"

@@ -422,6 +422,7 @@ void sdn_default_opts(sdn_opts *o) {
   o->max_points_per_item = 0;
   o->workspace_budget = 0;
   o->spread_engine = SDN_SPREAD_AUTO;
+  o->point_order = SDN_ORDER_AUTO;
 }
 
 const char *sdn_last_error(void) { return sdn::last_error(); }
@@ -467,6 +468,8 @@ sdn_status sdn_plan_create(sdn_plan *out, const int64_t shape[3], const float *t
   if (o.spread_engine < SDN_SPREAD_AUTO || o.spread_engine > SDN_SPREAD_MATRIX)
     return delete p, fail(SDN_E_INVALID, "sdn_plan_create: unknown spread_engine");
   p->spread_engine = o.spread_engine;
+  if (o.point_order != SDN_ORDER_AUTO && o.point_order != SDN_ORDER_CELL)
+    return delete p, fail(SDN_E_INVALID, "sdn_plan_create: unknown point_order");
   // library choice: kItemCap points per interpolation item, fewer (a power of
   // two, >= 512) for plans of under a million points so that they still
   // spread over enough workgroups
@@ -618,14 +621,15 @@ sdn_status sdn_plan_create(sdn_plan *out, const int64_t shape[3], const float *t
                          ord, rec_tmp, frame_of_point, m, tstart, ccount, p->rec, p->pidx);
       s = hip_check(hipGetLastError(), "plan placement kernel");
     }
-    // crowded tiles: reorder by first cell (stable, so ties keep the
-    // round-robin order); skipped when there are too many to key in 32 bits
+    // crowded tiles (every tile with SDN_ORDER_CELL): reorder by first cell
+    // (stable, so ties keep the round-robin order); skipped when there are
+    // too many to key in 32 bits
     if (s == SDN_OK) {
       const int ncell = (g.tile[0] + g.W - 1) * (g.tile[1] + g.W - 1) * (g.tile[2] + g.W - 1);
       std::vector<int> dtile, dstart, doff;
       int md = 0;
       for (int b = 0; b < nb; ++b)
-        if (2 * (int64_t)hcount[b] >= ncell && hcount[b] > 1) {
+        if ((o.point_order == SDN_ORDER_CELL || 2 * (int64_t)hcount[b] >= ncell) && hcount[b] > 1) {
           dtile.push_back(b);
           dstart.push_back(hstart[b]);
           doff.push_back(md);

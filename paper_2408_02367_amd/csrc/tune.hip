@@ -72,13 +72,16 @@ sdn_status sdn_autotune(const int64_t shape[3], const float *traj, int64_t M,
   std::vector<sdn_opts> cand;
   for (int tile : {0, 8, 16})
     for (int cap : {0, 1024})
-      for (int eng : {SDN_SPREAD_GATHER, SDN_SPREAD_MATRIX}) {
-        sdn_opts o = o0;
-        o.tile = tile;
-        o.max_points_per_item = cap;
-        o.spread_engine = eng;
-        cand.push_back(o);
-      }
+      for (int eng : {SDN_SPREAD_GATHER, SDN_SPREAD_MATRIX})
+        for (int order : {SDN_ORDER_AUTO, SDN_ORDER_CELL}) {
+          if (eng == SDN_SPREAD_MATRIX && order == SDN_ORDER_CELL) continue;
+          sdn_opts o = o0;
+          o.tile = tile;
+          o.max_points_per_item = cap;
+          o.spread_engine = eng;
+          o.point_order = order;
+          cand.push_back(o);
+        }
   hipEvent_t e0, e1;
   SDN_TRY_HIP(hipEventCreate(&e0), "autotune events");
   if (hipEventCreate(&e1) != hipSuccess) {

@@ -2,6 +2,8 @@
 the C ABI against the FP64 oracle (GPU), at sizes the oracle finishes in
 seconds that still span many tiles and ragged tails."""
 
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -178,6 +180,32 @@ def test_argument_errors(case):
     p.close()
     with pytest.raises(sdn.SdnError):
         sdn.mrf_forward(p, x, s, [0], V)
+
+
+def test_point_orders_agree(case, oracle_fwd):
+    """Every tile in cell order gives the same per-point sums (bit for bit:
+    a point's interpolation does not depend on its neighbours' order) and
+    the same adjoint up to the summation order; the library rejects an
+    unknown order."""
+    c = case
+    p, x, s, V = _gpu(c)
+    q, _, _, _ = _gpu(c, point_order="cell")
+    y0 = host(sdn.mrf_forward(p, x, s, c["coil_idx"], V))
+    y1 = host(sdn.mrf_forward(q, x, s, c["coil_idx"], V))
+    assert np.array_equal(y0, y1)
+    assert rel(y1, oracle_fwd) < TOL
+    r = c64(wl.random_kspace((c["B"], c["traj"].shape[0]), 33))
+    assert rel(host(sdn.mrf_adjoint(q, r, s, c["coil_idx"], V)),
+               host(sdn.mrf_adjoint(p, r, s, c["coil_idx"], V))) < 1e-6
+    o = sdn.Opts()
+    sdn.lib().sdn_default_opts(ctypes.byref(o))
+    o.point_order = 7
+    h = ctypes.c_void_p()
+    t = to_gpu(c["traj"])
+    st = sdn.lib().sdn_plan_create(ctypes.byref(h), (ctypes.c_int64 * 3)(*c["shape"]),
+                                   ctypes.c_void_p(t.data_ptr()), int(t.shape[0]), None, 1,
+                                   ctypes.byref(o), None)
+    assert st == -1 and not h.value   # SDN_E_INVALID
 
 
 @pytest.mark.parametrize("B", [8, 16, 6])

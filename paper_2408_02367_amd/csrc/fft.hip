@@ -266,11 +266,13 @@ k_fft_axis_ct(AxisArgs a) {
 // (q/d + 1) 2^-23, so the truncation is exact whenever q + d < 2^22.
 __device__ __forceinline__ int qdiv(int q, float inv) { return (int)(((float)q + 0.5f) * inv); }
 
-// Compile-time forward x pass: 16 lines per workgroup (line n = (z Ny + y) P + p).
-template <int L>
+constexpr int kPreLines = 8;   // lines per workgroup of the compile-time forward x pass
+
+// Compile-time forward x pass: C lines per workgroup (line n = (z Ny + y) P + p).
+template <int L, int C>
 __global__ void __launch_bounds__(kFftThreads)
 k_pre_fftx_ct(PreArgs a, float inv_nx, float inv_p) {
-  constexpr int C = 16, S = 17;
+  constexpr int S = C + 1;
   __shared__ float2 lds[L * S];
   __shared__ float2 tw[L];
   const LineGeom &g = a.g;
@@ -308,7 +310,7 @@ k_pre_fftx_ct(PreArgs a, float inv_nx, float inv_p) {
   __syncthreads();
   // every thread issues all its loads before using any (Nx <= L, so
   // C Nx <= C L elements cover the workgroup)
-  constexpr int NE = L * C / kFftThreads;
+  constexpr int NE = (L * C + kFftThreads - 1) / kFftThreads;
   float2 xv[NE], sv[NE];
 #pragma unroll
   for (int i = 0; i < NE; ++i) {
@@ -536,9 +538,12 @@ hipError_t launch_pre_fftx(const sdn_plan_s &p, const float2 *x, int K, const fl
   if (fft_len_ct(L) && nl_all + a.P < (1 << 22)) {
     const int64_t nl = nl_all;
     const float inv_nx = 1.0f / a.g.Nx, inv_p = 1.0f / a.P;
-    dim3 grd((unsigned)((nl + 15) / 16));
+    // 8 lines per workgroup: 22 KB of LDS at L = 320, so up to 7 workgroups
+    // share a CU and overlap their loads, transforms and stores
+    constexpr int C = kPreLines;
+    dim3 grd((unsigned)((nl + C - 1) / C));
 #define SDN_PRE_CT(LEN) \
-  case LEN: hipLaunchKernelGGL(k_pre_fftx_ct<LEN>, grd, dim3(kFftThreads), 0, st, a, inv_nx, inv_p); break;
+  case LEN: hipLaunchKernelGGL((k_pre_fftx_ct<LEN, C>), grd, dim3(kFftThreads), 0, st, a, inv_nx, inv_p); break;
     switch (L) {
       SDN_PRE_CT(64) SDN_PRE_CT(96) SDN_PRE_CT(128) SDN_PRE_CT(160) SDN_PRE_CT(192) SDN_PRE_CT(224) SDN_PRE_CT(256)
       SDN_PRE_CT(288) SDN_PRE_CT(320) SDN_PRE_CT(384) SDN_PRE_CT(400) SDN_PRE_CT(448)

@@ -404,16 +404,17 @@ k_ifftx_crop_ct(CropArgs a, float inv_nx) {
   }
 }
 
-// Inverse x pass fused with the coil combine, for B coils with B | 16: the
-// 16 columns of a workgroup are the B coils' lines of 16 / B image rows of
+// Inverse x pass fused with the coil combine, for B coils with B | C: the
+// C columns of a workgroup are the B coils' lines of C / B image rows of
 // one (channel k, plane z), column c = r B + b.  After the transform the
 // workgroup forms xout[k] (+)= sum_b conj(S_b) h_b / deapodisation for its
 // rows directly from LDS, so the cropped lines never go back to HBM.
-// Grid: (ceil(Ny / R), Nz, K) with R = 16 / B rows per workgroup.
-template <int L>
+// Grid: (ceil(Ny / R), Nz, K) with R = C / B rows per workgroup; C = 8
+// when B | 8 (twice the workgroups per CU of C = 16), else 16.
+template <int L, int C>
 __global__ void __launch_bounds__(kFftThreads)
 k_ifftx_post_ct(PostArgs a) {
-  constexpr int C = 16, S = 17;
+  constexpr int S = C + 1;
   __shared__ float2 lds[L * S];
   __shared__ float2 tw[L];
   __shared__ const float2 *col[C];
@@ -434,18 +435,19 @@ k_ifftx_post_ct(PostArgs a) {
   for (int m = tid; m < L; m += kFftThreads) tw[m] = a.tw[m];
   __syncthreads();
   {
-    constexpr int NE = L * C / kFftThreads;
+    constexpr int NE = (L * C + kFftThreads - 1) / kFftThreads;
+    constexpr bool whole = L * C % kFftThreads == 0;
     float2 v[NE];
 #pragma unroll
     for (int i = 0; i < NE; ++i) {
       const int e = tid + i * kFftThreads;
       const int l = e % L, c = e / L;
-      v[i] = col[c] ? col[c][l] : make_float2(0.f, 0.f);
+      v[i] = (whole || e < L * C) && col[c] ? col[c][l] : make_float2(0.f, 0.f);
     }
 #pragma unroll
     for (int i = 0; i < NE; ++i) {
       const int e = tid + i * kFftThreads;
-      lds[(e % L) * S + e / L] = v[i];
+      if (whole || e < L * C) lds[(e % L) * S + e / L] = v[i];
     }
   }
   __syncthreads();
@@ -581,10 +583,14 @@ hipError_t launch_post_ifftx(const sdn_plan_s &p, const float2 *grid, int K,
   a.tw = p.tw[0];
   a.rp = p.rp[0];
   if (fft_len_ct(L) && B <= 16 && 16 % B == 0 && a.g.Nz <= 65535 && K <= 65535) {
-    const int R = 16 / B;
+    const bool c8 = 8 % B == 0;
+    const int R = (c8 ? 8 : 16) / B;
     dim3 grd((unsigned)((a.g.Ny + R - 1) / R), (unsigned)a.g.Nz, (unsigned)K);
-#define SDN_POST_CT(LEN) \
-  case LEN: hipLaunchKernelGGL(k_ifftx_post_ct<LEN>, grd, dim3(kFftThreads), 0, st, a); break;
+#define SDN_POST_CT(LEN)                                                                    \
+  case LEN:                                                                                 \
+    if (c8) hipLaunchKernelGGL((k_ifftx_post_ct<LEN, 8>), grd, dim3(kFftThreads), 0, st, a); \
+    else hipLaunchKernelGGL((k_ifftx_post_ct<LEN, 16>), grd, dim3(kFftThreads), 0, st, a);   \
+    break;
     switch (L) {
       SDN_POST_CT(64) SDN_POST_CT(96) SDN_POST_CT(128) SDN_POST_CT(160) SDN_POST_CT(192)
       SDN_POST_CT(224) SDN_POST_CT(256) SDN_POST_CT(288) SDN_POST_CT(320) SDN_POST_CT(384)

@@ -227,11 +227,14 @@ k_fft_axis(AxisArgs a) {
   }
 }
 
-// Specialised strided pass: L and C = 16 columns known at compile time.
-template <bool INV, int L>
+// columns (consecutive x) per workgroup of the y and z passes: 16 read and
+// write whole 128-byte rows; 8 (64-byte segments) measured 1.4x slower
+constexpr int kAxisCols = 16;
+
+// Specialised strided pass: L and C columns known at compile time.
+template <bool INV, int L, int C>
 __global__ void __launch_bounds__(kFftThreads)
 k_fft_axis_ct(AxisArgs a) {
-  constexpr int C = 16;
   __shared__ float2 lds[L * C];
   __shared__ float2 tw[L];
   const int tid = threadIdx.x;
@@ -241,17 +244,20 @@ k_fft_axis_ct(AxisArgs a) {
   const int64_t plane = o2 < a.o_lo ? o2 : o2 + a.o_gap;
   float2 *base = a.data + o1 * a.so1 + plane * a.so2 + c0;
   for (int m = tid; m < L; m += kFftThreads) tw[m] = a.tw[m];
-  constexpr int NE = L * C / kFftThreads;   // L * C is a multiple of 256 for every specialisation
+  constexpr int NE = (L * C + kFftThreads - 1) / kFftThreads;
+  constexpr bool whole = L * C % kFftThreads == 0;
   float2 v[NE];
 #pragma unroll
   for (int q = 0; q < NE; ++q) {
     const int e = tid + q * kFftThreads;
     const int c = e % C, l = e / C;
-    v[q] = (l < a.in_lo || l >= a.in_lo + a.in_gap) ? base[(int64_t)l * a.I + c]
-                                                    : make_float2(0.f, 0.f);
+    v[q] = (whole || e < L * C) && (l < a.in_lo || l >= a.in_lo + a.in_gap)
+               ? base[(int64_t)l * a.I + c]
+               : make_float2(0.f, 0.f);
   }
 #pragma unroll
-  for (int q = 0; q < NE; ++q) lds[tid + q * kFftThreads] = v[q];
+  for (int q = 0; q < NE; ++q)
+    if (whole || tid + q * kFftThreads < L * C) lds[tid + q * kFftThreads] = v[q];
   __syncthreads();
   RadixSeq<L>::template run<INV, C, C, kFftThreads>(lds, tw);
   for (int e = tid; e < a.Lout * C; e += kFftThreads) {
@@ -683,13 +689,14 @@ hipError_t launch_fft_axis(const sdn_plan_s &p, float2 *grid, int P, int axis, b
   }
   const int64_t outer = (int64_t)P * a.O2;
   if (outer > 65535) return hipErrorInvalidValue;
-  if (a.I % 16 == 0) {
-    a.C = 16;
-    dim3 grd((unsigned)(a.I / 16), (unsigned)outer);
-#define SDN_AXIS_CT(LEN)                                                                     \
-  case LEN:                                                                                  \
-    if (inverse) hipLaunchKernelGGL((k_fft_axis_ct<true, LEN>), grd, dim3(kFftThreads), 0, st, a);  \
-    else hipLaunchKernelGGL((k_fft_axis_ct<false, LEN>), grd, dim3(kFftThreads), 0, st, a);         \
+  if (a.I % kAxisCols == 0) {
+    constexpr int C = kAxisCols;
+    a.C = C;
+    dim3 grd((unsigned)(a.I / C), (unsigned)outer);
+#define SDN_AXIS_CT(LEN)                                                                        \
+  case LEN:                                                                                     \
+    if (inverse) hipLaunchKernelGGL((k_fft_axis_ct<true, LEN, C>), grd, dim3(kFftThreads), 0, st, a); \
+    else hipLaunchKernelGGL((k_fft_axis_ct<false, LEN, C>), grd, dim3(kFftThreads), 0, st, a);        \
     return hipGetLastError();
     switch (a.L) {
       SDN_AXIS_CT(64)

@@ -84,7 +84,9 @@ typedef struct {
                               first cell) or SDN_ORDER_CELL (every tile by first
                               cell: more interpolation bank conflicts, but the
                               gather spreading of one-coil calls reads its points
-                              more coherently).  Results agree to rounding.       */
+                              more coherently; plans with more than 131072
+                              populated tiles keep the default order).  Results
+                              agree to rounding.                                   */
 } sdn_opts;
 
 /* Values of sdn_opts.spread_engine. */

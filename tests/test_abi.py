@@ -76,3 +76,38 @@ def test_host_side_errors():
     assert L.sdn_plan_get_info(None, ctypes.byref(info)) == -6
     with pytest.raises(sdn.SdnError):
         sdn.kernel_tables(7, 2.0, 8)
+
+
+def _header_struct_fields(name):
+    """Field names of `typedef struct { ... } name;` in the public header,
+    comments stripped, in declaration order."""
+    import re
+    src = open(os.path.join(os.path.dirname(__file__), "..", "include", "stodip_nufft.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    body = re.search(r"typedef struct \{([^}]*)\}\s*" + name + r"\s*;", src).group(1)
+    fields = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if decl:
+            fields += [re.sub(r"\[.*\]", "", f).strip().split()[-1] for f in decl.split(",")]
+    return fields
+
+
+def test_binding_structs_mirror_the_header():
+    assert [f for f, _ in sdn.Opts._fields_] == _header_struct_fields("sdn_opts")
+    info = [f for f, _ in sdn.PlanInfo._fields_]
+    hdr = _header_struct_fields("sdn_plan_info")
+    assert info == hdr
+
+
+def test_point_order_option_is_checked_on_the_host():
+    L = sdn.lib()
+    o = sdn.Opts()
+    L.sdn_default_opts(ctypes.byref(o))
+    assert (o.spread_engine, o.point_order) == (0, 0)
+    assert sdn.POINT_ORDERS == {"auto": 0, "cell": 1}
+    h = ctypes.c_void_p()
+    sh = (ctypes.c_int64 * 3)(8, 8, 8)
+    o.point_order = 7
+    assert L.sdn_plan_create(ctypes.byref(h), sh, None, 0, None, 0, ctypes.byref(o), None) == -1
+    assert b"point_order" in L.sdn_last_error()

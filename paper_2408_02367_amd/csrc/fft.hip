@@ -230,10 +230,14 @@ k_fft_axis(AxisArgs a) {
 // columns (consecutive x) per workgroup of the y and z passes: 16 read and
 // write whole 128-byte rows; 8 (64-byte segments) measured 1.4x slower
 constexpr int kAxisCols = 16;
+// threads per workgroup of the y and z passes: 512 (the same LDS as 256,
+// twice the waves to overlap its loads, transforms and stores; 11-17%
+// faster at L = 400)
+constexpr int kAxThreads = 512;
 
 // Specialised strided pass: L and C columns known at compile time.
 template <bool INV, int L, int C>
-__global__ void __launch_bounds__(kFftThreads)
+__global__ void __launch_bounds__(kAxThreads)
 k_fft_axis_ct(AxisArgs a) {
   __shared__ float2 lds[L * C];
   __shared__ float2 tw[L];
@@ -243,13 +247,13 @@ k_fft_axis_ct(AxisArgs a) {
   const int o1 = o / a.O2, o2 = o - o1 * a.O2;
   const int64_t plane = o2 < a.o_lo ? o2 : o2 + a.o_gap;
   float2 *base = a.data + o1 * a.so1 + plane * a.so2 + c0;
-  for (int m = tid; m < L; m += kFftThreads) tw[m] = a.tw[m];
-  constexpr int NE = (L * C + kFftThreads - 1) / kFftThreads;
-  constexpr bool whole = L * C % kFftThreads == 0;
+  for (int m = tid; m < L; m += kAxThreads) tw[m] = a.tw[m];
+  constexpr int NE = (L * C + kAxThreads - 1) / kAxThreads;
+  constexpr bool whole = L * C % kAxThreads == 0;
   float2 v[NE];
 #pragma unroll
   for (int q = 0; q < NE; ++q) {
-    const int e = tid + q * kFftThreads;
+    const int e = tid + q * kAxThreads;
     const int c = e % C, l = e / C;
     v[q] = (whole || e < L * C) && (l < a.in_lo || l >= a.in_lo + a.in_gap)
                ? base[(int64_t)l * a.I + c]
@@ -257,10 +261,10 @@ k_fft_axis_ct(AxisArgs a) {
   }
 #pragma unroll
   for (int q = 0; q < NE; ++q)
-    if (whole || tid + q * kFftThreads < L * C) lds[tid + q * kFftThreads] = v[q];
+    if (whole || tid + q * kAxThreads < L * C) lds[tid + q * kAxThreads] = v[q];
   __syncthreads();
-  RadixSeq<L>::template run<INV, C, C, kFftThreads>(lds, tw);
-  for (int e = tid; e < a.Lout * C; e += kFftThreads) {
+  RadixSeq<L>::template run<INV, C, C, kAxThreads>(lds, tw);
+  for (int e = tid; e < a.Lout * C; e += kAxThreads) {
     const int c = e % C, q = e / C;
     const int l = q < a.out_lo ? q : q + a.out_gap;
     base[(int64_t)l * a.I + c] = lds[l * C + c];
@@ -410,6 +414,11 @@ k_ifftx_crop_ct(CropArgs a, float inv_nx) {
   }
 }
 
+// threads per workgroup of the fused inverse x pass: 512 (0.57 -> 0.54 ms
+// at c4, 0.44 -> 0.33 ms at the 400-point lines of the paper shape; the
+// forward x pass stays at 256, which measured faster at c4)
+constexpr int kPostThreads = 512;
+
 // Inverse x pass fused with the coil combine, for B coils with B | C: the
 // C columns of a workgroup are the B coils' lines of C / B image rows of
 // one (channel k, plane z), column c = r B + b.  After the transform the
@@ -418,7 +427,7 @@ k_ifftx_crop_ct(CropArgs a, float inv_nx) {
 // Grid: (ceil(Ny / R), Nz, K) with R = C / B rows per workgroup; C = 8
 // when B | 8 (twice the workgroups per CU of C = 16), else 16.
 template <int L, int C>
-__global__ void __launch_bounds__(kFftThreads)
+__global__ void __launch_bounds__(kPostThreads)
 k_ifftx_post_ct(PostArgs a) {
   constexpr int S = C + 1;
   __shared__ float2 lds[L * S];
@@ -438,29 +447,29 @@ k_ifftx_post_ct(PostArgs a) {
       col[tid] = a.grid + (((size_t)(b * a.K + k) * g.nfz + zf) * g.nfy + yf) * L;
     }
   }
-  for (int m = tid; m < L; m += kFftThreads) tw[m] = a.tw[m];
+  for (int m = tid; m < L; m += kPostThreads) tw[m] = a.tw[m];
   __syncthreads();
   {
-    constexpr int NE = (L * C + kFftThreads - 1) / kFftThreads;
-    constexpr bool whole = L * C % kFftThreads == 0;
+    constexpr int NE = (L * C + kPostThreads - 1) / kPostThreads;
+    constexpr bool whole = L * C % kPostThreads == 0;
     float2 v[NE];
 #pragma unroll
     for (int i = 0; i < NE; ++i) {
-      const int e = tid + i * kFftThreads;
+      const int e = tid + i * kPostThreads;
       const int l = e % L, c = e / L;
       v[i] = (whole || e < L * C) && col[c] ? col[c][l] : make_float2(0.f, 0.f);
     }
 #pragma unroll
     for (int i = 0; i < NE; ++i) {
-      const int e = tid + i * kFftThreads;
+      const int e = tid + i * kPostThreads;
       if (whole || e < L * C) lds[(e % L) * S + e / L] = v[i];
     }
   }
   __syncthreads();
-  RadixSeq<L>::template run<true, C, S, kFftThreads>(lds, tw);
+  RadixSeq<L>::template run<true, C, S, kPostThreads>(lds, tw);
   const size_t nvox = (size_t)g.Nz * g.Ny * g.Nx;
   const float sz = a.dz[z];
-  for (int e = tid; e < R * g.Nx; e += kFftThreads) {
+  for (int e = tid; e < R * g.Nx; e += kPostThreads) {
     const int r = e / g.Nx, xq = e - r * g.Nx;
     const int y = y0 + r;
     if (y >= g.Ny) continue;
@@ -594,8 +603,8 @@ hipError_t launch_post_ifftx(const sdn_plan_s &p, const float2 *grid, int K,
     dim3 grd((unsigned)((a.g.Ny + R - 1) / R), (unsigned)a.g.Nz, (unsigned)K);
 #define SDN_POST_CT(LEN)                                                                    \
   case LEN:                                                                                 \
-    if (c8) hipLaunchKernelGGL((k_ifftx_post_ct<LEN, 8>), grd, dim3(kFftThreads), 0, st, a); \
-    else hipLaunchKernelGGL((k_ifftx_post_ct<LEN, 16>), grd, dim3(kFftThreads), 0, st, a);   \
+    if (c8) hipLaunchKernelGGL((k_ifftx_post_ct<LEN, 8>), grd, dim3(kPostThreads), 0, st, a); \
+    else hipLaunchKernelGGL((k_ifftx_post_ct<LEN, 16>), grd, dim3(kPostThreads), 0, st, a);   \
     break;
     switch (L) {
       SDN_POST_CT(64) SDN_POST_CT(96) SDN_POST_CT(128) SDN_POST_CT(160) SDN_POST_CT(192)
@@ -695,8 +704,8 @@ hipError_t launch_fft_axis(const sdn_plan_s &p, float2 *grid, int P, int axis, b
     dim3 grd((unsigned)(a.I / C), (unsigned)outer);
 #define SDN_AXIS_CT(LEN)                                                                        \
   case LEN:                                                                                     \
-    if (inverse) hipLaunchKernelGGL((k_fft_axis_ct<true, LEN, C>), grd, dim3(kFftThreads), 0, st, a); \
-    else hipLaunchKernelGGL((k_fft_axis_ct<false, LEN, C>), grd, dim3(kFftThreads), 0, st, a);        \
+    if (inverse) hipLaunchKernelGGL((k_fft_axis_ct<true, LEN, C>), grd, dim3(kAxThreads), 0, st, a); \
+    else hipLaunchKernelGGL((k_fft_axis_ct<false, LEN, C>), grd, dim3(kAxThreads), 0, st, a);        \
     return hipGetLastError();
     switch (a.L) {
       SDN_AXIS_CT(64)

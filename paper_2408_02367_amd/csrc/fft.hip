@@ -230,13 +230,12 @@ k_fft_axis(AxisArgs a) {
 // columns (consecutive x) per workgroup of the y and z passes: 16 read and
 // write whole 128-byte rows; 8 (64-byte segments) measured 1.4x slower
 constexpr int kAxisCols = 16;
-// threads per workgroup of the y and z passes: 512 (the same LDS as 256,
-// twice the waves to overlap its loads, transforms and stores; 11-17%
-// faster at L = 400)
-constexpr int kAxThreads = 512;
+// threads per workgroup of the y and z passes: 512 for L >= 128 (the same
+// LDS as 256, twice the waves to overlap its loads, transforms and stores;
+// 11-17% faster at L = 400), 256 for the short lines of small grids
 
 // Specialised strided pass: L and C columns known at compile time.
-template <bool INV, int L, int C>
+template <bool INV, int L, int C, int kAxThreads>
 __global__ void __launch_bounds__(kAxThreads)
 k_fft_axis_ct(AxisArgs a) {
   __shared__ float2 lds[L * C];
@@ -704,8 +703,11 @@ hipError_t launch_fft_axis(const sdn_plan_s &p, float2 *grid, int P, int axis, b
     dim3 grd((unsigned)(a.I / C), (unsigned)outer);
 #define SDN_AXIS_CT(LEN)                                                                        \
   case LEN:                                                                                     \
-    if (inverse) hipLaunchKernelGGL((k_fft_axis_ct<true, LEN, C>), grd, dim3(kAxThreads), 0, st, a); \
-    else hipLaunchKernelGGL((k_fft_axis_ct<false, LEN, C>), grd, dim3(kAxThreads), 0, st, a);        \
+    {                                                                                           \
+      constexpr int NT = LEN >= 128 ? 512 : 256;                                                \
+      if (inverse) hipLaunchKernelGGL((k_fft_axis_ct<true, LEN, C, NT>), grd, dim3(NT), 0, st, a); \
+      else hipLaunchKernelGGL((k_fft_axis_ct<false, LEN, C, NT>), grd, dim3(NT), 0, st, a);        \
+    }                                                                                           \
     return hipGetLastError();
     switch (a.L) {
       SDN_AXIS_CT(64)

@@ -276,10 +276,13 @@ k_fft_axis_ct(AxisArgs a) {
 __device__ __forceinline__ int qdiv(int q, float inv) { return (int)(((float)q + 0.5f) * inv); }
 
 constexpr int kPreLines = 8;   // lines per workgroup of the compile-time forward x pass
+// its threads per workgroup: 512 for lines of 384 points and more (0.33 ->
+// 0.29 ms at L = 400), 256 below (512 measured slower at L = 320)
+constexpr int kPreThreads(int L) { return L >= 384 ? 512 : 256; }
 
 // Compile-time forward x pass: C lines per workgroup (line n = (z Ny + y) P + p).
-template <int L, int C>
-__global__ void __launch_bounds__(kFftThreads)
+template <int L, int C, int NT>
+__global__ void __launch_bounds__(NT)
 k_pre_fftx_ct(PreArgs a, float inv_nx, float inv_p) {
   constexpr int S = C + 1;
   __shared__ float2 lds[L * S];
@@ -311,19 +314,19 @@ k_pre_fftx_ct(PreArgs a, float inv_nx, float inv_p) {
       orow[tid] = a.grid + (((size_t)p * g.nfz + zf) * g.nfy + yf) * L;
     }
   }
-  for (int m = tid; m < L; m += kFftThreads) tw[m] = a.tw[m];
-  for (int e = tid; e < (L - g.Nx) * C; e += kFftThreads) {
+  for (int m = tid; m < L; m += NT) tw[m] = a.tw[m];
+  for (int e = tid; e < (L - g.Nx) * C; e += NT) {
     const int c = e % C, r = e / C;
     lds[((g.Nx - g.hx) + r) * S + c] = make_float2(0.f, 0.f);
   }
   __syncthreads();
   // every thread issues all its loads before using any (Nx <= L, so
   // C Nx <= C L elements cover the workgroup)
-  constexpr int NE = (L * C + kFftThreads - 1) / kFftThreads;
+  constexpr int NE = (L * C + NT - 1) / NT;
   float2 xv[NE], sv[NE];
 #pragma unroll
   for (int i = 0; i < NE; ++i) {
-    const int e = tid + i * kFftThreads;
+    const int e = tid + i * NT;
     xv[i] = sv[i] = make_float2(0.f, 0.f);
     if (e < C * g.Nx) {
       const int c = qdiv(e, inv_nx);
@@ -336,7 +339,7 @@ k_pre_fftx_ct(PreArgs a, float inv_nx, float inv_p) {
   }
 #pragma unroll
   for (int i = 0; i < NE; ++i) {
-    const int e = tid + i * kFftThreads;
+    const int e = tid + i * NT;
     if (e < C * g.Nx) {
       const int c = qdiv(e, inv_nx);
       const int xq = e - c * g.Nx;
@@ -348,8 +351,8 @@ k_pre_fftx_ct(PreArgs a, float inv_nx, float inv_p) {
     }
   }
   __syncthreads();
-  RadixSeq<L>::template run<false, C, S, kFftThreads>(lds, tw);
-  for (int e = tid; e < C * L; e += kFftThreads) {
+  RadixSeq<L>::template run<false, C, S, NT>(lds, tw);
+  for (int e = tid; e < C * L; e += NT) {
     const int l = e % L, c = e / L;
     if (orow[c]) orow[c][l] = lds[l * S + c];
   }
@@ -559,7 +562,7 @@ hipError_t launch_pre_fftx(const sdn_plan_s &p, const float2 *x, int K, const fl
     constexpr int C = kPreLines;
     dim3 grd((unsigned)((nl + C - 1) / C));
 #define SDN_PRE_CT(LEN) \
-  case LEN: hipLaunchKernelGGL((k_pre_fftx_ct<LEN, C>), grd, dim3(kFftThreads), 0, st, a, inv_nx, inv_p); break;
+  case LEN: hipLaunchKernelGGL((k_pre_fftx_ct<LEN, C, kPreThreads(LEN)>), grd, dim3(kPreThreads(LEN)), 0, st, a, inv_nx, inv_p); break;
     switch (L) {
       SDN_PRE_CT(64) SDN_PRE_CT(96) SDN_PRE_CT(128) SDN_PRE_CT(160) SDN_PRE_CT(192) SDN_PRE_CT(224) SDN_PRE_CT(256)
       SDN_PRE_CT(288) SDN_PRE_CT(320) SDN_PRE_CT(384) SDN_PRE_CT(400) SDN_PRE_CT(448)

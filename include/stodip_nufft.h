@@ -254,8 +254,9 @@ SDN_API sdn_status sdn_mrf_adjoint_plain(sdn_plan plan, const void *y, int K, co
 SDN_API sdn_status sdn_dcf_estimate(sdn_plan plan, int iterations, float *w_out, void *stream);
 
 /*
- * Initialisers of the TSMI x^(0) (Sec. 2.3 starts the network from an
- * estimate of the inverse problem of Eq. 1: the SVD-MRF adjoint with a
+ * Initialisers of the TSMI x^(0) (Sec. 2.2, "Initialisation of x^(0)",
+ * starts the network from an estimate of the inverse problem of Eq. 1:
+ * the SVD-MRF adjoint with a
  * scaling factor, and low-rank least squares by conjugate gradients, with
  * or without Tikhonov regularisation).  The paper names the three only;
  * the operators here, over the B listed coils with the DCF weight

@@ -16,6 +16,9 @@ What it computes (Sec. 2, Eq. 1-3 of the paper):
 * ``gridding`` - the oversampled gridding NUFFT (deapodise, zero-pad, FFT,
                  interpolate; and the exact adjoint: spread, IFFT, crop,
                  deapodise), step by step in FP64.
+* ``cloops``   - the same node sums as ``gridding``'s interpolation and
+                 spreading, as plain C loops over several grids at once
+                 (``gridding_loops.c``), for full-size comparisons.
 * ``mrf``      - the MRF forward operator A_c (coil sensitivities, NUFFT,
                  temporal-subspace mix), its adjoint, the data-consistency
                  loss of Eq. 2-3 and its gradient 2 A^H w (A x - d), plus a
@@ -24,7 +27,7 @@ What it computes (Sec. 2, Eq. 1-3 of the paper):
                  fixed-point iteration with the gridding kernel.
 * ``tv``       - the total-variation penalty of Alg. 1 (StoDIP + TV) and its
                  gradient.
-* ``recon``    - the initialisers of Sec. 2.3: normal operator over all
+* ``recon``    - the initialisers of Sec. 2.2: normal operator over all
                  coils, conjugate gradients (with and without Tikhonov) and
                  the scaled adjoint.
 
@@ -33,4 +36,4 @@ something other than itself (library FFTs on on-grid points, closed forms,
 Parseval, adjoint identities, quadrature, brute-force loops).
 """
 
-from . import nudft, kernel, gridding, mrf, dcf, tv, recon  # noqa: F401
+from . import nudft, kernel, gridding, cloops, mrf, dcf, tv, recon  # noqa: F401

@@ -2,7 +2,7 @@
 
 Test infrastructure only.
 
-Sec. 2.3 starts the network from an estimate of the inverse problem of
+Sec. 2.2 starts the network from an estimate of the inverse problem of
 Eq. 1 rather than from noise, by (a) the SVD-MRF adjoint with a scaling
 factor, (b) low-rank least squares by conjugate gradients and (c) the same
 with Tikhonov regularisation.  The paper names the three and no more; the

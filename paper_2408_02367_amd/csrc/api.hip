@@ -66,6 +66,17 @@ sdn_status ensure_part(sdn_plan_s *p, int groups, int K) {
   return s;
 }
 
+sdn_status ensure_lpart(sdn_plan_s *p, int groups) {
+  const size_t n = interp_loss_parts(*p, groups) + kSumChunks;
+  if (p->lpart_cap >= n) return SDN_OK;
+  if (p->lpart) (void)hipFree(p->lpart);
+  p->lpart = nullptr;
+  p->lpart_cap = 0;
+  sdn_status s = hip_check(hipMalloc((void **)&p->lpart, n * sizeof(double)), "loss partials");
+  if (s == SDN_OK) p->lpart_cap = n;
+  return s;
+}
+
 // Channels of P-channel grids that fit the workspace budget at once.
 sdn_status channels_per_pass(const sdn_plan_s &p, int unit, int units, int *per,
                              const char *fn) {
@@ -141,24 +152,32 @@ CoilList coil_list(const int32_t *idx, int b0, int n) {
 
 // forward stages for one chunk of coils: grid <- FFT3(pad(deapod(S x)))
 sdn_status forward_grid(sdn_plan_s *p, const float2 *x, int K, const float2 *smaps,
-                        const CoilList &coils, int B, hipStream_t st) {
+                        const CoilList &coils, int B, float2 *grid, hipStream_t st) {
   const int P = B * K;
-  SDN_STAGE(p, SDN_STAGE_PRE_FFTX, launch_pre_fftx(*p, x, K, smaps, coils, B, p->grid, st), "forward x pass");
-  SDN_STAGE(p, SDN_STAGE_FFT_Y, launch_fft_axis(*p, p->grid, P, 1, false, true, false, st), "forward y pass");
-  SDN_STAGE(p, SDN_STAGE_FFT_Z, launch_fft_axis(*p, p->grid, P, 2, false, true, false, st), "forward z pass");
+  SDN_STAGE(p, SDN_STAGE_PRE_FFTX, launch_pre_fftx(*p, x, K, smaps, coils, B, grid, st), "forward x pass");
+  SDN_STAGE(p, SDN_STAGE_FFT_Y, launch_fft_axis(*p, grid, P, 1, false, true, false, st), "forward y pass");
+  SDN_STAGE(p, SDN_STAGE_FFT_Z, launch_fft_axis(*p, grid, P, 2, false, true, false, st), "forward z pass");
   return SDN_OK;
+}
+sdn_status forward_grid(sdn_plan_s *p, const float2 *x, int K, const float2 *smaps,
+                        const CoilList &coils, int B, hipStream_t st) {
+  return forward_grid(p, x, K, smaps, coils, B, p->grid, st);
 }
 
 // adjoint stages after spreading: x_out (+)= sum_b conj(S_b) crop(IFFT3(grid)) / deapod
 sdn_status adjoint_grid(sdn_plan_s *p, int K, const float2 *smaps, const CoilList &coils, int B,
-                        float2 *xout, int accumulate, hipStream_t st) {
+                        float2 *xout, int accumulate, float2 *grid, hipStream_t st) {
   const int P = B * K;
-  SDN_STAGE(p, SDN_STAGE_IFFT_Z, launch_fft_axis(*p, p->grid, P, 2, true, false, true, st), "adjoint z pass");
-  SDN_STAGE(p, SDN_STAGE_IFFT_Y, launch_fft_axis(*p, p->grid, P, 1, true, false, true, st), "adjoint y pass");
+  SDN_STAGE(p, SDN_STAGE_IFFT_Z, launch_fft_axis(*p, grid, P, 2, true, false, true, st), "adjoint z pass");
+  SDN_STAGE(p, SDN_STAGE_IFFT_Y, launch_fft_axis(*p, grid, P, 1, true, false, true, st), "adjoint y pass");
   SDN_STAGE(p, SDN_STAGE_POST_IFFTX,
-            launch_post_ifftx(*p, p->grid, K, smaps, coils, B, xout, accumulate, st),
+            launch_post_ifftx(*p, grid, K, smaps, coils, B, xout, accumulate, st),
             "adjoint x pass");
   return SDN_OK;
+}
+sdn_status adjoint_grid(sdn_plan_s *p, int K, const float2 *smaps, const CoilList &coils, int B,
+                        float2 *xout, int accumulate, hipStream_t st) {
+  return adjoint_grid(p, K, smaps, coils, B, xout, accumulate, p->grid, st);
 }
 
 __global__ void k_zero_c64(float2 *a, size_t n) {
@@ -209,6 +228,7 @@ sdn_status normal_pass(sdn_plan_s *p, const float2 *x, int K, const float2 *smap
   int per;
   SDN_TRY(channels_per_pass(*p, K, B, &per, "normal operator"));
   SDN_TRY(ensure_kbuf(p, (size_t)per * p->M));
+  SDN_TRY(ensure_lpart(p, per));
   for (int b0 = 0; b0 < B; b0 += per) {
     const int bc = std::min(per, B - b0);
     const CoilList coils = coil_list(coil_idx, b0, bc);
@@ -226,6 +246,7 @@ sdn_status normal_pass(sdn_plan_s *p, const float2 *x, int K, const float2 *smap
     a.w = w;
     a.r_plan = p->kbuf;
     a.loss = loss;
+    a.loss_part = p->lpart;
     a.rmax = p->absmax;
     SDN_STAGE(p, SDN_STAGE_INTERP, launch_interp(*p, a, st), "interpolation + weighting");
     if (!adjoint) continue;
@@ -270,6 +291,69 @@ sdn_status rhs_pass(sdn_plan_s *p, const float2 *y, int K, const float2 *smaps,
     s.src_plan_order = true;
     SDN_STAGE(p, SDN_STAGE_SPREAD, launch_spread(*p, s, st), "spreading");
     SDN_TRY(adjoint_grid(p, K, smaps, coils, bc, out, b0 > 0 ? 1 : 0, st));
+  }
+  return SDN_OK;
+}
+
+// Buffers of one DC-gradient call for `per` coils at a time: fine grids
+// (per K channels), plan-order residuals (per coils), spreading partials and
+// the interpolation's loss partials.
+struct DcWork {
+  float2 *grid;
+  float2 *kbuf;
+  float2 *part;
+  double *lpart;
+};
+
+// Complex elements (grid, kbuf, part) and doubles (lpart) that DcWork
+// needs for `per` coils of K channels.
+void dc_work_sizes(const sdn_plan_s &p, int per, int K, size_t *grid, size_t *kbuf, size_t *part,
+                   size_t *lpart) {
+  *grid = (size_t)per * K * fine_cells(p);
+  *grid += *grid & 1;   // whole float4s for the fill kernel
+  *kbuf = (size_t)per * p.M;
+  *part = spread_part_elems(p, per, K);
+  *lpart = interp_loss_parts(p, per) + kSumChunks;
+}
+
+// loss = sum_b w |A_b x - d_b|^2 and grad = 2 A^H w (A x - d), coils in
+// chunks of `per` (the arguments have been checked).
+sdn_status dc_grad_pass(sdn_plan_s *p, const DcWork &ws, int per, const float2 *x, int K,
+                        const float2 *smaps, const int32_t *coil_idx, int B, const float2 *V,
+                        const float2 *d, const float *w, double *loss, float2 *grad,
+                        hipStream_t st) {
+  SDN_HIP(launch_fill_zero_f64(loss, 1, st), "loss clear");
+  if (p->M == 0) return zero_user(grad, (size_t)K * image_voxels(*p), st);
+  for (int b0 = 0; b0 < B; b0 += per) {
+    const int bc = std::min(per, B - b0);
+    const CoilList coils = coil_list(coil_idx, b0, bc);
+    SDN_TRY(forward_grid(p, x, K, smaps, coils, bc, ws.grid, st));
+    InterpArgs a{};
+    a.grid = ws.grid;
+    a.P = bc * K;
+    a.groups = bc;
+    a.kg = K;
+    a.V = V;
+    a.dc = 1;
+    a.rscale = 2.f;
+    a.d = d + (size_t)b0 * p->M;
+    a.w = w;
+    a.r_plan = ws.kbuf;
+    a.loss = loss;
+    a.loss_part = ws.lpart;
+    a.rmax = p->absmax;
+    SDN_STAGE(p, SDN_STAGE_INTERP, launch_interp(*p, a, st), "interpolation + residual");
+    SpreadArgs s{};
+    s.grid = ws.grid;
+    s.part = ws.part;
+    s.groups = bc;
+    s.K = K;
+    s.V = V;
+    s.src = ws.kbuf;
+    s.src_plan_order = true;
+    s.src_max_ready = true;   // recorded by the interpolation above
+    SDN_STAGE(p, SDN_STAGE_SPREAD, launch_spread(*p, s, st), "spreading");
+    SDN_TRY(adjoint_grid(p, K, smaps, coils, bc, grad, b0 > 0 ? 1 : 0, ws.grid, st));
   }
   return SDN_OK;
 }
@@ -403,46 +487,17 @@ sdn_status sdn_mrf_dc_grad(sdn_plan p, const void *x, int K, const void *smaps, 
   SDN_TRY(check_mrf_args(*p, "sdn_mrf_dc_grad", x, K, smaps, C, coil_idx, B, V, d));
   if (!loss || !grad) return fail(SDN_E_INVALID, "sdn_mrf_dc_grad: null output argument");
   hipStream_t st = (hipStream_t)stream;
-  SDN_HIP(launch_fill_zero_f64(loss, 1, st), "loss clear");
-  if (p->M == 0) return zero_user((float2 *)grad, (size_t)K * image_voxels(*p), st);
-  int per;
-  SDN_TRY(channels_per_pass(*p, K, B, &per, "sdn_mrf_dc_grad"));
-  SDN_TRY(ensure_kbuf(p, (size_t)per * p->M));
-  for (int b0 = 0; b0 < B; b0 += per) {
-    const int bc = std::min(per, B - b0);
-    const CoilList coils = coil_list(coil_idx, b0, bc);
-    const size_t cells = (size_t)bc * K * fine_cells(*p);
-    SDN_TRY(ensure_grid(p, cells));
-    SDN_TRY(forward_grid(p, (const float2 *)x, K, (const float2 *)smaps, coils, bc, st));
-    InterpArgs a{};
-    a.grid = p->grid;
-    a.P = bc * K;
-    a.groups = bc;
-    a.kg = K;
-    a.V = (const float2 *)V;
-    a.dc = 1;
-    a.rscale = 2.f;
-    a.d = (const float2 *)d + (size_t)b0 * p->M;
-    a.w = w;
-    a.r_plan = p->kbuf;
-    a.loss = loss;
-    a.rmax = p->absmax;
-    SDN_STAGE(p, SDN_STAGE_INTERP, launch_interp(*p, a, st), "interpolation + residual");
-    SDN_TRY(ensure_part(p, bc, K));
-    SpreadArgs s{};
-    s.grid = p->grid;
-    s.part = p->part;
-    s.groups = bc;
-    s.K = K;
-    s.V = (const float2 *)V;
-    s.src = p->kbuf;
-    s.src_plan_order = true;
-    s.src_max_ready = true;   // recorded by the interpolation above
-    SDN_STAGE(p, SDN_STAGE_SPREAD, launch_spread(*p, s, st), "spreading");
-    SDN_TRY(adjoint_grid(p, K, (const float2 *)smaps, coils, bc, (float2 *)grad, b0 > 0 ? 1 : 0,
-                         st));
+  int per = 1;
+  if (p->M > 0) {
+    SDN_TRY(channels_per_pass(*p, K, B, &per, "sdn_mrf_dc_grad"));
+    SDN_TRY(ensure_kbuf(p, (size_t)per * p->M));
+    SDN_TRY(ensure_grid(p, (size_t)per * K * fine_cells(*p)));
+    SDN_TRY(ensure_part(p, per, K));
+    SDN_TRY(ensure_lpart(p, per));
   }
-  return SDN_OK;
+  const DcWork ws{p->grid, p->kbuf, p->part, p->lpart};
+  return dc_grad_pass(p, ws, per, (const float2 *)x, K, (const float2 *)smaps, coil_idx, B,
+                      (const float2 *)V, (const float2 *)d, w, loss, (float2 *)grad, st);
 }
 
 sdn_status sdn_mrf_forward_plain(sdn_plan p, const void *x, int K, const void *smaps, int C,
@@ -651,8 +706,9 @@ sdn_status sdn_workspace_size(sdn_plan p, int B, int K, size_t *bytes) {
   if (!bytes || B < 1 || K < 1) return fail(SDN_E_INVALID, "sdn_workspace_size: bad argument");
   int per;
   SDN_TRY(channels_per_pass(*p, K, B, &per, "sdn_workspace_size"));
-  *bytes = ((size_t)per * K * fine_cells(*p) + (size_t)per * p->M +
-            spread_part_elems(*p, per, K)) * sizeof(float2);
+  size_t g, kb, pt, lp;
+  dc_work_sizes(*p, per, K, &g, &kb, &pt, &lp);
+  *bytes = (g + kb + pt) * sizeof(float2) + lp * sizeof(double);
   return SDN_OK;
 }
 
@@ -692,12 +748,14 @@ sdn_status sdn_release_workspace(sdn_plan p) {
   if (p->part) (void)hipFree(p->part);
   if (p->vecbuf) (void)hipFree(p->vecbuf);
   if (p->red) (void)hipFree(p->red);
+  if (p->lpart) (void)hipFree(p->lpart);
   p->grid = nullptr;
   p->kbuf = nullptr;
   p->part = nullptr;
   p->vecbuf = nullptr;
   p->red = nullptr;
-  p->grid_cap = p->kbuf_cap = p->part_cap = p->vecbuf_cap = p->red_cap = 0;
+  p->lpart = nullptr;
+  p->grid_cap = p->kbuf_cap = p->part_cap = p->vecbuf_cap = p->red_cap = p->lpart_cap = 0;
   return SDN_OK;
 }
 

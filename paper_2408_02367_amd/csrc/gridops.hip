@@ -71,7 +71,7 @@ struct InterpDev {
   const float2 *d;
   const float *w;
   float2 *r_plan;
-  double *loss;
+  double *loss_part;   // DC mode: one partial loss per workgroup, [groups][items]
   float rscale;
   unsigned *rmax;
 };
@@ -251,7 +251,9 @@ __global__ void __launch_bounds__(kIThreads) k_interp(InterpDev a) {
           mx = fmaxf(mx, pmax[i]);
         }
         if (a.rmax) atomicMax(a.rmax, __float_as_uint(mx));
-        atomicAdd(a.loss, s);
+        // the partials are summed afterwards in a fixed order, so the loss
+        // does not depend on the order in which workgroups finish
+        a.loss_part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
       }
     }
   }
@@ -966,22 +968,30 @@ hipError_t launch_interp(const sdn_plan_s &p, const InterpArgs &a, hipStream_t s
   d.d = a.d;
   d.w = a.w;
   d.r_plan = a.r_plan;
-  d.loss = a.loss;
+  d.loss_part = a.loss_part;
   d.rscale = a.rscale;
   d.rmax = a.dc ? a.rmax : nullptr;
   const bool mix = a.V != nullptr;
   const bool dc = a.dc != 0;
-  if (dc && (!mix || a.r_plan == nullptr || a.loss == nullptr)) return hipErrorInvalidValue;
+  if (dc && (!mix || a.r_plan == nullptr || a.loss == nullptr || a.loss_part == nullptr))
+    return hipErrorInvalidValue;
   const size_t lds = interp_lds_bytes(p);
   if (lds > max_lds_bytes()) return hipErrorInvalidValue;
   if (d.rmax) hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, d.rmax, 1);
   dim3 grd((unsigned)p.nwork, (unsigned)a.groups);
+  hipError_t e;
   switch (p.W) {
-    case 4: return interp_launch<4>(d, mix, dc, grd, lds, st);
-    case 8: return interp_launch<8>(d, mix, dc, grd, lds, st);
-    default: return interp_launch<6>(d, mix, dc, grd, lds, st);
+    case 4: e = interp_launch<4>(d, mix, dc, grd, lds, st); break;
+    case 8: e = interp_launch<8>(d, mix, dc, grd, lds, st); break;
+    default: e = interp_launch<6>(d, mix, dc, grd, lds, st); break;
   }
+  if (e != hipSuccess || !dc) return e;
+  // loss += the workgroups' partials, two fixed-order levels
+  const size_t nparts = interp_loss_parts(p, a.groups);
+  return launch_sum(a.loss_part, (int)nparts, 1.0, a.loss, st, a.loss_part + nparts, true);
 }
+
+size_t interp_loss_parts(const sdn_plan_s &p, int groups) { return (size_t)p.nwork * groups; }
 
 size_t spread_part_elems(const sdn_plan_s &p, int groups, int K) {
   return (size_t)p.nslots * groups * K * kSBCells;

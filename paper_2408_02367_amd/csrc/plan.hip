@@ -381,6 +381,9 @@ void free_plan_memory(sdn_plan_s *p) {
   if (p->sitems) (void)hipFree(p->sitems);
   if (p->splits) (void)hipFree(p->splits);
   if (p->part) (void)hipFree(p->part);
+  if (p->lpart) (void)hipFree(p->lpart);
+  p->lpart = nullptr;
+  p->lpart_cap = 0;
   p->vlist = nullptr;
   p->sitems = nullptr;
   p->splits = nullptr;
@@ -671,8 +674,8 @@ sdn_status sdn_plan_create(sdn_plan *out, const int64_t shape[3], const float *t
           s = hip_check(hipGetLastError(), "plan dense placement kernels");
         }
         if (s == SDN_OK) s = hip_check(hipStreamSynchronize(st), "plan sync");
-        hipFree(ddev);
-        hipFree(ptmp);
+        (void)hipFree(ddev);
+        (void)hipFree(ptmp);
       }
     }
     // per-point kernel weights

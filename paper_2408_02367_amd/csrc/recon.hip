@@ -1,6 +1,6 @@
 // Image-space kernels around the operator: the total-variation penalty of
 // Alg. 1 (StoDIP + TV) and the reductions and vector updates of the
-// conjugate-gradient and scaled-adjoint initialisers of Sec. 2.3.
+// conjugate-gradient and scaled-adjoint initialisers of Sec. 2.2.
 //
 // All of these are HBM-bound streams over K image volumes.  Sums are taken
 // in FP64 in two fixed-order passes (per-block partials, then one block),
@@ -46,11 +46,12 @@ __global__ void __launch_bounds__(kRedThreads) k_dot(const float2 *__restrict__ 
 }
 
 __global__ void __launch_bounds__(kRedThreads) k_sum(const double *__restrict__ part, int n,
-                                                     double scale, double *__restrict__ out) {
+                                                     double scale, double *__restrict__ out,
+                                                     int accumulate) {
   double s = 0.0;
   for (int i = threadIdx.x; i < n; i += kRedThreads) s += part[i];
   s = block_sum(s);
-  if (threadIdx.x == 0) *out = scale * s;
+  if (threadIdx.x == 0) *out = accumulate ? *out + scale * s : scale * s;
 }
 
 // First level of a long sum: block b adds the b-th contiguous chunk.
@@ -265,14 +266,15 @@ hipError_t launch_dot(const float2 *a, const float2 *b, size_t n, double *part, 
 }
 
 hipError_t launch_sum(const double *part, int n, double scale, double *out, hipStream_t st,
-                      double *scratch) {
+                      double *scratch, bool accumulate) {
   if (scratch && n > 16 * kRedThreads) {
     hipLaunchKernelGGL(k_sum_chunks, dim3(kSumChunks), dim3(kRedThreads), 0, st, part, n,
                        scratch);
     part = scratch;
     n = kSumChunks;
   }
-  hipLaunchKernelGGL(k_sum, dim3(1), dim3(kRedThreads), 0, st, part, n, scale, out);
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(kRedThreads), 0, st, part, n, scale, out,
+                     accumulate ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -123,6 +123,8 @@ struct sdn_plan_s {
   size_t kbuf_cap = 0;
   float2 *part = nullptr;    // partial tiles of split spreading items
   size_t part_cap = 0;
+  double *lpart = nullptr;   // per-workgroup partial losses of a DC interpolation
+  size_t lpart_cap = 0;
   unsigned *absmax = nullptr; // 4 words: largest input magnitudes of a spreading call
   int spread_engine = 0;      // SDN_SPREAD_*
 
@@ -153,11 +155,11 @@ hipError_t launch_fill_zero_f64(double *a, size_t n, hipStream_t st);
 constexpr int kDotBlocks = 1024;
 // part[0 .. kDotBlocks) = partial sums of Re <a, b> over n complex elements
 hipError_t launch_dot(const float2 *a, const float2 *b, size_t n, double *part, hipStream_t st);
-// *out = scale * sum(part[0 .. n)); with scratch (kSumChunks doubles) a long
-// sum runs in two fixed-order levels
+// *out = scale * sum(part[0 .. n)) (*out += ... when accumulate); with
+// scratch (kSumChunks doubles) a long sum runs in two fixed-order levels
 constexpr int kSumChunks = 256;
 hipError_t launch_sum(const double *part, int n, double scale, double *out, hipStream_t st,
-                      double *scratch = nullptr);
+                      double *scratch = nullptr, bool accumulate = false);
 // out[j][g] = scale w[orig(j)] y[g][orig(j)], plan order, for g < groups
 hipError_t launch_weighted_plan(const sdn_plan_s &p, const float2 *y, int groups, const float *w,
                                 float scale, float2 *out, hipStream_t st);
@@ -218,10 +220,13 @@ struct InterpArgs {
   const float *w;   // [M] user order, or null
   float2 *r_plan;   // [M][groups] plan order, a point's coils side by side
   double *loss;
+  double *loss_part;  // interp_loss_parts(p, groups) + kSumChunks doubles of scratch
   unsigned *rmax;   // DC mode, or null: set to the largest |component| of r
                     // (as float bits), for the spreading that follows
 };
 hipError_t launch_interp(const sdn_plan_s &p, const InterpArgs &a, hipStream_t st);
+// Per-workgroup loss partials of a DC interpolation over `groups` coils.
+size_t interp_loss_parts(const sdn_plan_s &p, int groups);
 size_t interp_lds_bytes(const sdn_plan_s &p);
 size_t max_lds_bytes();
 

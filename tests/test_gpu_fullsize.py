@@ -7,7 +7,12 @@
   T = 1000 frames x 8 interleaves x 1200 samples (M = 9.6M), W = 6,
   sigma = 2 - in the launch configuration the benchmark times: outputs at
   seeded random points (forward) and voxels (adjoint) against the direct
-  NUDFT computed one by one, plus properties that hold at any size.
+  NUDFT computed one by one; one (coil, channel) type 2 and type 1 over
+  the whole output array against the FP64 gridding oracle; the autograd
+  gradient of the DC loss (d = A x_true + 1% noise from the FP64 oracle,
+  x a 10% smooth perturbation of x_true) against the fused DC gradient and
+  against 2 A^H (A x - d) from the oracle at sampled voxels; plus
+  properties that hold at any size.
 """
 
 import numpy as np
@@ -18,7 +23,7 @@ import paper_2408_02367_amd as sdn
 import workloads as wl
 from gpu_common import (TOL, c64, cimg, direct_adjoint_at, direct_forward_at, host, rel, to_gpu,
                         uniform_points)
-from oracle import gridding, nudft
+from oracle import cloops, gridding, nudft
 from oracle import mrf as omrf
 
 pytestmark = pytest.mark.gpu
@@ -124,3 +129,87 @@ def test_benchmark_size_dc_gradient_is_exact_directional_derivative(big):
     fd = (lp.item() - lm.item()) / (2 * eps)
     an = torch.vdot(g.flatten().to(torch.complex128), dx.flatten().to(torch.complex128)).real.item()
     assert abs(fd - an) / abs(an) < 1e-4
+
+
+@pytest.fixture(scope="module")
+def big_nodes(big):
+    """The FP64 oracle's kernel nodes of the 9.6M benchmark points."""
+    g = gridding.Grid(big["w"]["shape"])
+    return g, cloops.node_chunks(g, big["w"]["traj"])
+
+
+def test_benchmark_size_type2_full_array_vs_gridding(big, big_nodes):
+    """One (coil, channel) of the benchmark: plain type 2 of S_c x_k at all
+    9.6M points against the FP64 gridding NUFFT with the same kernel."""
+    w, p = big["w"], big["plan"]
+    g, nodes = big_nodes
+    f = (w["smaps"][w["coil_idx"][0]] * w["x"][0]).astype(np.complex64)
+    y = host(p.forward(c64(f[None])))[0]
+    ref = cloops.interp_many(g, g.fft(g.deapodise_pad(f.astype(np.complex128))), w["traj"],
+                             nodes=nodes)[0]
+    assert rel(y, ref) < 5e-6
+    # the k-space centre (the densest tiles) on its own
+    centre = np.arange(0, w["traj"].shape[0], 1200)
+    assert rel(y[centre], ref[centre]) < 5e-6
+
+
+def test_benchmark_size_type1_full_array_vs_gridding(big, big_nodes):
+    """Plain type 1 of one row of random k-space values at all 9.6M points,
+    compared over the whole 160^3 image."""
+    w, p = big["w"], big["plan"]
+    g, nodes = big_nodes
+    r = wl.random_kspace((1, w["traj"].shape[0]), 16)
+    img = host(p.adjoint(c64(r)))[0]
+    ref = g.crop_deapodise(g.ifft(cloops.spread_many(g, r, w["traj"], nodes=nodes)[0]))
+    assert rel(img, ref) < 5e-6
+
+
+def test_benchmark_size_autograd_gradient_vs_oracle(big, big_nodes):
+    """MRFForward + loss.backward() at the benchmark size: equal to the fused
+    DC gradient, and to the oracle's 2 A^H (A x - d) at sampled voxels, with
+    d = A x_true + 1% complex noise made by the FP64 oracle and x = x_true +
+    a smooth perturbation of 10% RMS (so |A x - d| is about 0.1 |d|)."""
+    w, p = big["w"], big["plan"]
+    g, nodes = big_nodes
+    shape, K = w["shape"], w["K"]
+    ci = w["coil_idx"]
+    B, M = len(ci), w["traj"].shape[0]
+    x_true = w["x"].astype(np.complex64)
+    pert = wl.phantom(shape, K, w["seed"] + 100)
+    pert *= 0.1 * np.sqrt(np.mean(np.abs(x_true) ** 2) / np.mean(np.abs(pert) ** 2))
+    x = (x_true + pert).astype(np.complex64)
+    V = w["V"].astype(np.complex128)
+    Vt = V[w["frame"]]                                         # [M, K]
+
+    def oracle_forward(img):
+        y = np.zeros((B, M), dtype=np.complex128)
+        for b, c in enumerate(ci):
+            S = w["smaps"][c].astype(np.complex128)
+            Gs = np.stack([g.fft(g.deapodise_pad(S * img[k].astype(np.complex128)))
+                           for k in range(K)])
+            u = cloops.interp_many(g, Gs, w["traj"], nodes=nodes)
+            del Gs
+            y[b] = np.sum(Vt.T * u, axis=0)
+        return y
+
+    y_true = oracle_forward(x_true)
+    rms = np.sqrt(np.mean(np.abs(y_true) ** 2, axis=1))
+    d = (y_true + wl.complex_noise((B, M), 0.01, rms, w["seed"])).astype(np.complex64)
+    r = oracle_forward(x) - d.astype(np.complex128)
+    assert 0.03 < np.linalg.norm(r) / np.linalg.norm(d) < 0.3
+
+    xr = c64(x).requires_grad_(True)
+    dd = c64(d)
+    y = sdn.MRFForward.apply(xr, p, big["s"], big["ci_local"], big["V"])
+    loss = torch.sum(torch.view_as_real(y - dd).double() ** 2)
+    loss.backward()
+    l_dc, g_dc = sdn.mrf_dc_grad(p, c64(x), big["s"], big["ci_local"], big["V"], dd)
+    assert rel(host(xr.grad), host(g_dc)) < 1e-6
+    assert abs(loss.item() - l_dc.item()) <= 1e-6 * l_dc.item()
+    l_ref = float(np.sum(np.abs(r) ** 2))
+    assert abs(l_dc.item() - l_ref) <= 1e-4 * l_ref
+
+    sel = ([5, 40, 81, 120, 158], [2, 77, 80, 141], [0, 33, 80, 112, 159])
+    ref = 2.0 * direct_adjoint_at(w, r, sel)
+    gs = host(g_dc)[(slice(None),) + np.ix_(*sel)]
+    assert rel(gs, ref) < TOL

@@ -192,6 +192,26 @@ SDN_API sdn_status sdn_mrf_dc_grad(sdn_plan plan, const void *x, int K, const vo
                            const float *w, double *loss, void *grad, void *stream);
 
 /*
+ * The DC loss and gradient of sdn_mrf_dc_grad (same arguments, same
+ * results), for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  It
+ * calls no allocating routine.  Its fine grids, residuals and partial sums
+ * live in a static device array of SDN_NOALLOC_SCRATCH_BYTES inside the
+ * library (one per GPU, held until the process ends), and coils are
+ * processed in passes of as many as fit in it (the plan's workspace budget
+ * does not apply).  SDN_E_NOMEM when one coil's K grids, its residuals and
+ * partial sums exceed it (e.g. K = 5 on a 64^3 fine grid fits; on 320^3 it
+ * does not).  Every call on one GPU, for any plan and on any stream, uses
+ * that one array and leaves it holding its last contents: calls that
+ * overlap on one GPU race, so the caller serialises them.
+ */
+#define SDN_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+SDN_API sdn_status sdn_mrf_dc_grad_noalloc(sdn_plan plan, const void *x, int K, const void *smaps,
+                                           int C, const int32_t *coil_idx, int B, const void *V,
+                                           const void *d, const float *w, double *loss,
+                                           void *grad, void *stream);
+
+/*
  * Ragged volumes: a group of plans of different image shapes, each with its
  * own trajectory (and V), evaluated as one call on one stream (the batched
  * form over several volumes; Sec. 3 reconstructs many scans with one

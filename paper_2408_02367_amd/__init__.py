@@ -36,7 +36,7 @@ API = ["sdn_default_opts", "sdn_plan_create", "sdn_plan_destroy", "sdn_plan_get_
        "sdn_kernel_tables", "sdn_last_error", "sdn_group_create", "sdn_group_destroy",
        "sdn_group_mrf_forward", "sdn_group_mrf_adjoint", "sdn_group_mrf_dc_grad",
        "sdn_autotune", "sdn_dcf_estimate", "sdn_mrf_normal", "sdn_mrf_cg",
-       "sdn_mrf_scaled_adjoint", "sdn_tv_grad"]
+       "sdn_mrf_scaled_adjoint", "sdn_tv_grad", "sdn_mrf_dc_grad_noalloc"]
 
 # stage names, in the order of the sdn_stage enum
 STAGES = ["pre_fftx", "fft_y", "fft_z", "interp", "clear", "spread", "ifft_z", "ifft_y",
@@ -94,6 +94,7 @@ def lib():
         L.sdn_mrf_adjoint.argtypes = mrf + [i32, vp]
         L.sdn_mrf_adjoint_plain.argtypes = mrf + [i32, vp]
         L.sdn_mrf_dc_grad.argtypes = mrf + [vp, vp, vp, vp]
+        L.sdn_mrf_dc_grad_noalloc.argtypes = mrf + [vp, vp, vp, vp]
         L.sdn_workspace_size.argtypes = [vp, i32, i32, ctypes.POINTER(ctypes.c_size_t)]
         L.sdn_release_workspace.argtypes = [vp]
         L.sdn_profile_enable.argtypes = [vp, i32]

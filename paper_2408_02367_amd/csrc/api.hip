@@ -9,6 +9,7 @@
 // forward's fine grids are never kept for the adjoint: A is linear, so its
 // adjoint needs none of them, and the same workspace serves both.
 #include <algorithm>
+#include <mutex>
 #include <string>
 
 #include "sdn_internal.h"
@@ -356,6 +357,57 @@ sdn_status dc_grad_pass(sdn_plan_s *p, const DcWork &ws, int per, const float2 *
     SDN_TRY(adjoint_grid(p, K, smaps, coils, bc, grad, b0 > 0 ? 1 : 0, ws.grid, st));
   }
   return SDN_OK;
+}
+
+// ------------------------------------------- the DC gradient without allocation
+// Buffers of sdn_mrf_dc_grad_noalloc: one array per GPU in the code object,
+// held until the process ends.  In host code `scratch` is a host-side
+// stand-in; its device address is looked up once per device.
+static __device__ __align__(256) unsigned char scratch[SDN_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+
+struct ScratchAddrs {
+  std::mutex m;
+  unsigned char *ptr[kMaxDevices] = {};
+};
+
+ScratchAddrs &scratch_addrs() {
+  static ScratchAddrs s;
+  return s;
+}
+
+// Device address of `scratch` on `device` (looked up with that device
+// current, on the first call for it).
+sdn_status scratch_on(int device, unsigned char **out) {
+  if (device < 0 || device >= kMaxDevices)
+    return fail(SDN_E_UNSUPPORTED, "sdn_mrf_dc_grad_noalloc: device index out of range");
+  ScratchAddrs &s = scratch_addrs();
+  std::lock_guard<std::mutex> lock(s.m);
+  if (s.ptr[device] == nullptr) {
+    int cur = -1;
+    SDN_HIP(hipGetDevice(&cur), "sdn_mrf_dc_grad_noalloc: current device");
+    if (cur != device) SDN_HIP(hipSetDevice(device), "sdn_mrf_dc_grad_noalloc: set device");
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != device) (void)hipSetDevice(cur);
+    SDN_HIP(e, "sdn_mrf_dc_grad_noalloc: static workspace address");
+    if (ptr == nullptr) return fail(SDN_E_HIP, "sdn_mrf_dc_grad_noalloc: no static workspace");
+    s.ptr[device] = (unsigned char *)ptr;
+  }
+  *out = s.ptr[device];
+  return SDN_OK;
+}
+
+size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
+
+// Bytes of the DcWork of `per` coils carved from one block (256-byte
+// aligned pieces).
+size_t dc_work_bytes(const sdn_plan_s &p, int per, int K) {
+  size_t g, kb, pt, lp;
+  dc_work_sizes(p, per, K, &g, &kb, &pt, &lp);
+  return align256(g * sizeof(float2)) + align256(kb * sizeof(float2)) +
+         align256(pt * sizeof(float2)) + align256(lp * sizeof(double));
 }
 
 }  // namespace
@@ -757,6 +809,43 @@ sdn_status sdn_release_workspace(sdn_plan p) {
   p->lpart = nullptr;
   p->grid_cap = p->kbuf_cap = p->part_cap = p->vecbuf_cap = p->red_cap = p->lpart_cap = 0;
   return SDN_OK;
+}
+
+sdn_status sdn_mrf_dc_grad_noalloc(sdn_plan p, const void *x, int K, const void *smaps, int C,
+                                   const int32_t *coil_idx, int B, const void *V, const void *d,
+                                   const float *w, double *loss, void *grad, void *stream) {
+  SDN_TRY(check_plan(p, "sdn_mrf_dc_grad_noalloc"));
+  SDN_TRY(check_mrf_args(*p, "sdn_mrf_dc_grad_noalloc", x, K, smaps, C, coil_idx, B, V, d));
+  if (!loss || !grad) return fail(SDN_E_INVALID, "sdn_mrf_dc_grad_noalloc: null output argument");
+  unsigned char *base = nullptr;
+  SDN_TRY(scratch_on(p->device, &base));
+  // the most coils per pass whose buffers fit the static workspace
+  int per = B;
+  while (per > 1 && dc_work_bytes(*p, per, K) > SDN_NOALLOC_SCRATCH_BYTES) --per;
+  if (p->M > 0 && dc_work_bytes(*p, per, K) > SDN_NOALLOC_SCRATCH_BYTES)
+    return fail(SDN_E_NOMEM, "sdn_mrf_dc_grad_noalloc: one coil's grids, residuals and partial "
+                             "sums (" + std::to_string(dc_work_bytes(*p, 1, K)) +
+                             " bytes) exceed the static workspace (" +
+                             std::to_string((size_t)SDN_NOALLOC_SCRATCH_BYTES) + " bytes)");
+  size_t g, kb, pt, lp;
+  dc_work_sizes(*p, per, K, &g, &kb, &pt, &lp);
+  DcWork ws;
+  unsigned char *q = base;
+  ws.grid = (float2 *)q;
+  q += align256(g * sizeof(float2));
+  ws.kbuf = (float2 *)q;
+  q += align256(kb * sizeof(float2));
+  ws.part = (float2 *)q;
+  q += align256(pt * sizeof(float2));
+  ws.lpart = (double *)q;
+  // no stage events either: recording them may create events
+  const int prof = p->prof;
+  p->prof = 0;
+  const sdn_status s = dc_grad_pass(p, ws, per, (const float2 *)x, K, (const float2 *)smaps,
+                                    coil_idx, B, (const float2 *)V, (const float2 *)d, w, loss,
+                                    (float2 *)grad, (hipStream_t)stream);
+  p->prof = prof;
+  return s;
 }
 
 }  // extern "C"

@@ -71,12 +71,17 @@ typedef struct {
                               whose coil minibatch does not fit run coil-chunked.   */
   int spread_engine;       /* type-1 spreading kernel: SDN_SPREAD_AUTO (default:
                               the matrix cores when a call spreads >= 2 coils of
-                              >= 2 channels, else the gather), SDN_SPREAD_GATHER
-                              (vector ALU gather into registers) or
-                              SDN_SPREAD_MATRIX (matrix cores, split fp16 products
-                              with FP32 accumulation; for the subspace calls with
-                              >= 2 channels and every fine axis >= 16, else the
-                              gather runs; the plain type-1 call always gathers)   */
+                              >= 2 channels - split by planes from 32 (coil,
+                              channel) pairs, by coils below - else the gather),
+                              SDN_SPREAD_GATHER (vector ALU gather into
+                              registers), SDN_SPREAD_MATRIX (matrix cores, one
+                              wave per coil, split fp16 products with FP32
+                              accumulation) or SDN_SPREAD_PLANES (matrix cores,
+                              waves split by block planes, the value operand
+                              built once for all coils and channels).  The
+                              matrix engines serve the subspace calls with >= 2
+                              channels and every fine axis >= 16, else the
+                              gather runs; the plain type-1 call always gathers.  */
   int point_order;         /* order of the points within an interpolation tile:
                               SDN_ORDER_AUTO (default: round-robin over the 32
                               LDS residue classes of their first cell, tiles with
@@ -90,7 +95,7 @@ typedef struct {
 } sdn_opts;
 
 /* Values of sdn_opts.spread_engine. */
-enum { SDN_SPREAD_AUTO = 0, SDN_SPREAD_GATHER = 1, SDN_SPREAD_MATRIX = 2 };
+enum { SDN_SPREAD_AUTO = 0, SDN_SPREAD_GATHER = 1, SDN_SPREAD_MATRIX = 2, SDN_SPREAD_PLANES = 3 };
 
 /* Values of sdn_opts.point_order. */
 enum { SDN_ORDER_AUTO = 0, SDN_ORDER_CELL = 1 };
@@ -110,7 +115,8 @@ typedef struct {
   int ncoef;               /* coefficients per piece of the kernel polynomial        */
   int64_t nvisit;          /* (point, tile) pairs of the spreading lists             */
   int spread_engine;       /* engine a call with >= 2 coils of >= 2 channels
-                              uses: SDN_SPREAD_GATHER or SDN_SPREAD_MATRIX           */
+                              uses: SDN_SPREAD_GATHER, _MATRIX or _PLANES; see
+                              sdn_spread_engine for a given minibatch              */
 } sdn_plan_info;
 
 /* Library defaults: W = 6, sigma = 2, automatic tiles, no budget. */
@@ -139,6 +145,11 @@ SDN_API sdn_status sdn_plan_create(sdn_plan *out, const int64_t shape[3], const 
 SDN_API sdn_status sdn_plan_destroy(sdn_plan plan);
 
 SDN_API sdn_status sdn_plan_get_info(sdn_plan plan, sdn_plan_info *info);
+
+/* Spreading engine (SDN_SPREAD_GATHER, _MATRIX or _PLANES) that the subspace
+ * calls of this plan use for a minibatch of B coils of K channels, into
+ * *engine (host int).  SDN_E_INVALID for B or K below 1 or a NULL engine. */
+SDN_API sdn_status sdn_spread_engine(sdn_plan plan, int B, int K, int *engine);
 
 /*
  * Plain type-2 NUFFT of `batch` images (uniform -> nonuniform):

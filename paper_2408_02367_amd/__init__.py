@@ -36,7 +36,8 @@ API = ["sdn_default_opts", "sdn_plan_create", "sdn_plan_destroy", "sdn_plan_get_
        "sdn_kernel_tables", "sdn_last_error", "sdn_group_create", "sdn_group_destroy",
        "sdn_group_mrf_forward", "sdn_group_mrf_adjoint", "sdn_group_mrf_dc_grad",
        "sdn_autotune", "sdn_dcf_estimate", "sdn_mrf_normal", "sdn_mrf_cg",
-       "sdn_mrf_scaled_adjoint", "sdn_tv_grad", "sdn_mrf_dc_grad_noalloc"]
+       "sdn_mrf_scaled_adjoint", "sdn_tv_grad", "sdn_mrf_dc_grad_noalloc",
+       "sdn_spread_engine"]
 
 # stage names, in the order of the sdn_stage enum
 STAGES = ["pre_fftx", "fft_y", "fft_z", "interp", "clear", "spread", "ifft_z", "ifft_y",
@@ -55,8 +56,9 @@ class Opts(ctypes.Structure):
                 ("spread_engine", ctypes.c_int), ("point_order", ctypes.c_int)]
 
 
-SPREAD_ENGINES = {"auto": 0, "gather": 1, "matrix": 2}
+SPREAD_ENGINES = {"auto": 0, "gather": 1, "matrix": 2, "planes": 3}
 POINT_ORDERS = {"auto": 0, "cell": 1}
+_ENGINE_NAMES = {1: "gather", 2: "matrix", 3: "planes"}
 
 
 class PlanInfo(ctypes.Structure):
@@ -86,6 +88,7 @@ def lib():
                                       ctypes.c_int32, ctypes.POINTER(Opts), vp]
         L.sdn_plan_destroy.argtypes = [vp]
         L.sdn_plan_get_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
+        L.sdn_spread_engine.argtypes = [vp, i32, i32, ctypes.POINTER(i32)]
         L.sdn_forward.argtypes = [vp, vp, vp, i32, vp]
         L.sdn_adjoint.argtypes = [vp, vp, vp, i32, vp]
         mrf = [vp, vp, i32, vp, i32, ctypes.POINTER(ctypes.c_int32), i32, vp, vp]
@@ -219,7 +222,13 @@ class Plan:
         return dict(shape=tuple(i.shape), fine=tuple(i.fine), M=i.M, T=i.T, W=i.W,
                     sigma=i.sigma, beta=i.beta, tile=tuple(i.tile), nbins=i.nbins,
                     nwork=i.nwork, max_bin=i.max_bin, ncoef=i.ncoef, nvisit=i.nvisit,
-                    spread_engine={1: "gather", 2: "matrix"}.get(i.spread_engine, "gather"))
+                    spread_engine=_ENGINE_NAMES.get(i.spread_engine, "gather"))
+
+    def spread_engine(self, B, K):
+        """Spreading engine of the subspace calls for B coils of K channels."""
+        e = ctypes.c_int()
+        _check(lib().sdn_spread_engine(self.handle, int(B), int(K), ctypes.byref(e)))
+        return _ENGINE_NAMES[e.value]
 
     def workspace_size(self, B, K):
         n = ctypes.c_size_t()

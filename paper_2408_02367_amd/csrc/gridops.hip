@@ -795,6 +795,320 @@ __global__ void __launch_bounds__(64 * NG) k_spread_mma(SpreadDev a, const unsig
   }
 }
 
+// ---------------------------------------------------------------------------
+// Spreading as a matrix product, split by planes (many coils and channels).
+//
+// For one 8 x 8 x 8 block and the coils g of a workgroup, the sum over the
+// block's list entries p is, plane by plane,
+//   H_z[(y,x), (g,k,re/im)] = sum_p A_z[(y,x), p] B[p, (g,k,re/im)],
+//   A_z = wz_p(z) wy_p(y) wx_p(x),   B = r_g(p) conj(V[t_p][k]),
+// products of 16 x 32 and 32 x 16 tiles (v_mfma_f32_16x16x32_f16, 32 list
+// entries per step).  FP32 accuracy is kept by splitting each operand into
+// fp16 hi + lo parts (x = hi + lo to ~2^-22) and summing the three products
+// hi.hi + hi.lo + lo.hi in the FP32 accumulators; the values are scaled by
+// a power of two s (from the largest input magnitude) so that they sit in
+// fp16 range, and the block is scaled back by 1/s on write-out.
+//
+// Work split: the value operand B does not depend on the plane, so each of
+// its 16-column tiles is built once per batch (by one wave) into LDS; the
+// sixteen waves of the workgroup split the 32 (plane, y-pair) row tiles,
+// wave w taking two y pairs of plane w / 2, and build their A tiles
+// themselves.  A block's list is sorted by the z offset of the points, so
+// the supports of one batch cover few planes: a wave whose plane no entry
+// of the batch touches skips the batch (its operand build and products).
+// The entries' data are loaded by two alternating sets of eight waves (one
+// 16-byte piece per lane: a piece of a weight record, two basis values or
+// two residuals), two batches ahead of their use, and their list entries
+// two batches ahead of that.  Used when every fine axis is at least 16
+// cells, so that no kernel support can touch both ends of a block.
+constexpr int kPwWaves = 16;                  // waves of a plane-split workgroup
+constexpr int kPwCols = 96;                   // value columns per workgroup at most
+// Weight rows of the plane-split kernel are 26 floats apart: the four lane
+// groups of a fragment read rows of entries 8 apart, which then start 16
+// banks apart instead of on the same banks.
+constexpr int kPwRow = 26;
+
+// Coils of one plane-split workgroup for kernel width W and K channels:
+// 2 K value columns each, at most kPwCols, and few enough that one fetch
+// set (512 lanes) loads a batch: W record pieces, ceil(K/2) basis pieces
+// and ceil(G/2) residual pieces per entry.
+__host__ __device__ constexpr int pw_coils(int W, int K) {
+  const int by_cols = kPwCols / (2 * K);
+  const int by_fetch = 2 * (512 / kMmaBatch - W - (K + 1) / 2);
+  const int g = by_cols < by_fetch ? by_cols : by_fetch;
+  return g < 16 ? g : 16;
+}
+
+// A lane's list entry: plan index of the point, (frame, original index).
+struct PwList {
+  int j;
+  int2 id;
+};
+
+template <int W, int K, int NCT>
+__global__ void __launch_bounds__(64 * kPwWaves) k_spread_pw(SpreadDev a, const unsigned *absmax) {
+  constexpr int GMAX = pw_coils(W, K);        // coils of a full workgroup
+  constexpr int NVP = (K + 1) / 2;            // basis pieces per entry
+  constexpr int NRP = (GMAX + 1) / 2;         // residual pieces per entry
+  static_assert(kMmaBatch * (W + NVP + NRP) <= 512, "one fetch set loads a batch");
+  // double-buffered staging: batch n is staged into buffer n & 1 one
+  // iteration ahead; its value tiles are built into buffer n & 1 and its A
+  // tiles into registers before the barrier of iteration n, and the
+  // products run after it
+  __shared__ float wrow[2][3][kMmaBatch][kPwRow];
+  __shared__ int shifts[2][kMmaBatch];        // x, y, z row shifts; plane mask in bits 24..31
+  __shared__ float2 vbas[2][kMmaBatch][2 * NVP];
+  __shared__ float2 rsd[2][kMmaBatch][2 * NRP];
+  __shared__ uint4 sB[2][NCT][2][64];         // [buffer][column tile][hi/lo][lane]
+
+  const int4 it = a.items[blockIdx.x];
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  const int g0 = blockIdx.y * GMAX;
+  const int G = min(GMAX, a.groups - g0);     // coils of this workgroup
+  const int bzi = it.x / (a.nbx * a.nby);
+  const int rem = it.x - bzi * (a.nbx * a.nby);
+  const int byi = rem / a.nbx, bxi = rem - byi * a.nbx;
+  const int ox = bxi * kSB, oy = byi * kSB, oz = bzi * kSB;
+  const float s = value_scale(absmax, true);
+  const int nb = (it.z + kMmaBatch - 1) / kMmaBatch;
+
+  // zero the weight rows once; each batch rewrites only the W weights
+  for (int i = tid; i < 2 * 3 * kMmaBatch * kPwRow; i += 64 * kPwWaves) (&wrow[0][0][0][0])[i] = 0.f;
+
+  // this wave's row tiles: y pairs 2 h and 2 h + 1 of plane z
+  const int z = wv >> 1, h = wv & 1;
+  sdn_float4v acc[2][NCT];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int c = 0; c < NCT; ++c) acc[t][c] = sdn_float4v{0.f, 0.f, 0.f, 0.f};
+
+  const int r16 = lane & 15;              // fragment row (A) / column (B)
+  const int e0 = 8 * (lane >> 4);         // fragment entries e0 .. e0+7
+  const int fx = r16 & 7, fy = 4 * h + (r16 >> 3);   // A: x, and y of the first tile
+
+  // fetch set (wv / 8) loads the batches of its parity; lane q of the set
+  // takes one 16-byte piece of entry pe: a weight-record piece (q < 32 W),
+  // two basis values, or two residuals
+  const int q = (wv & 7) * 64 + lane;
+  const int set = wv >> 3;
+  int kind, pe, pc;
+  if (q < kMmaBatch * W) {
+    kind = 0; pe = q / W; pc = q - pe * W;
+  } else if (q < kMmaBatch * (W + NVP)) {
+    kind = 1; pe = (q - kMmaBatch * W) / NVP; pc = q - kMmaBatch * W - pe * NVP;
+  } else if (q < kMmaBatch * (W + NVP + NRP)) {
+    kind = 2; pe = (q - kMmaBatch * (W + NVP)) / NRP; pc = q - kMmaBatch * (W + NVP) - pe * NRP;
+  } else {
+    kind = 3; pe = 0; pc = 0;
+  }
+  PwList L{0, make_int2(0, 0)};
+  float4 fv = make_float4(0.f, 0.f, 0.f, 0.f);
+  // list entry of batch b for this lane's piece
+  auto list = [&](int b) {
+    const int e = b * kMmaBatch + pe;
+    if (kind == 3 || e >= it.z) return;
+    const int raw = a.vlist[it.y + e];
+    // a complemented entry is a support that starts in an earlier block (z
+    // offset below 0); on grids of at least 16 cells per axis no support
+    // meets a block twice, so it is an ordinary entry here
+    L.j = raw < 0 ? ~raw : raw;
+    if (kind != 0) L.id = a.vinfo[it.y + e];
+  };
+  // this lane's 16-byte piece of batch b (zeros past the list's end)
+  auto fetch = [&](int b) {
+    fv = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (kind == 3 || b * kMmaBatch + pe >= it.z) return;
+    if (kind == 0) {
+      fv = reinterpret_cast<const float4 *>(a.wts + (size_t)L.j * wrec_stride(W))[pc];
+    } else if (kind == 1) {
+      const int k = 2 * pc;
+      const float2 v0 = a.V[(size_t)L.id.x * K + k];
+      const float2 v1 = k + 1 < K ? a.V[(size_t)L.id.x * K + k + 1] : make_float2(0.f, 0.f);
+      fv = make_float4(v0.x, v0.y, v1.x, v1.y);
+    } else {
+      const int c = 2 * pc;
+      float2 r0 = make_float2(0.f, 0.f), r1 = make_float2(0.f, 0.f);
+      if (a.src_plan) {
+        const float2 *sp = a.src + (size_t)L.j * a.groups + g0 + c;
+        if (c < G) r0 = sp[0];
+        if (c + 1 < G) r1 = sp[1];
+      } else {
+        if (c < G) r0 = a.src[(size_t)(g0 + c) * a.M + L.id.y];
+        if (c + 1 < G) r1 = a.src[(size_t)(g0 + c + 1) * a.M + L.id.y];
+      }
+      fv = make_float4(r0.x, r0.y, r1.x, r1.y);
+    }
+  };
+  // store this lane's piece of batch b into buffer bf
+  auto stage = [&](int bf, int b) {
+    if (kind == 0) {
+      const float v[4] = {fv.x, fv.y, fv.z, fv.w};
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = 4 * pc + u;          // float of the record
+        if (i < 3 * W) {
+          wrow[bf][i / W][pe][kWinPad + i % W] = v[u];
+        } else if (i == 3 * W) {
+          // the first node: row shifts and the planes the support covers
+          const unsigned bits = __float_as_uint(v[u]);
+          const int sx = win_shift(ox, (int)(bits & 1023u), a.nfx, W);
+          const int sy = win_shift(oy, (int)((bits >> 10) & 1023u), a.nfy, W);
+          const int sz = win_shift(oz, (int)((bits >> 20) & 1023u), a.nfz, W);
+          const int lo = max(0, -sz), hi = min(kSB, W - sz);
+          const unsigned mask = (b * kMmaBatch + pe < it.z && hi > lo)
+                                    ? ((1u << hi) - 1u) & ~((1u << lo) - 1u) : 0u;
+          shifts[bf][pe] = (sx + kWinPad) | ((sy + kWinPad) << 8) | ((sz + kWinPad) << 16) |
+                           (int)(mask << 24);
+        }
+      }
+    } else if (kind == 1) {
+      vbas[bf][pe][2 * pc] = make_float2(fv.x, fv.y);
+      vbas[bf][pe][2 * pc + 1] = make_float2(fv.z, fv.w);
+    } else if (kind == 2) {
+      rsd[bf][pe][2 * pc] = make_float2(fv.x, fv.y);
+      rsd[bf][pe][2 * pc + 1] = make_float2(fv.z, fv.w);
+    }
+  };
+  // the value tile c of batch bf (wave c builds it): column n of the tile
+  // is (coil, channel, re/im) = 16 c + n, its 8 entries e0 .. e0 + 7
+  auto build_values = [&](int bf, int vb) {
+    if (wv < NCT) {
+      const int col = 16 * wv + r16;
+      const int gl = col / (2 * K), kk = (col >> 1) - gl * K, ri = col & 1;
+      float v[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        float x = 0.f;
+        if (gl < G) {
+          const float2 m = cmulc(rsd[vb][e0 + e][gl], vbas[vb][e0 + e][kk]);
+          x = (ri ? m.y : m.x) * s;
+        }
+        v[e] = x;
+      }
+      unsigned hi[4], lo[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) split2(v[2 * e], v[2 * e + 1], hi[e], lo[e]);
+      sB[bf][wv][0][lane] = make_uint4(hi[0], hi[1], hi[2], hi[3]);
+      sB[bf][wv][1][lane] = make_uint4(lo[0], lo[1], lo[2], lo[3]);
+    }
+  };
+
+  // prologue: set 0 stages batch 0 and holds batch 2 and the list of batch
+  // 4; set 1 holds batch 1 and the list of batch 3
+  if (set == 0) {
+    list(0);
+    fetch(0);
+    list(2);
+  } else {
+    list(1);
+    fetch(1);
+    list(3);
+  }
+  __syncthreads();   // rows zeroed
+  if (set == 0 && nb > 0) {
+    stage(0, 0);
+    fetch(2);
+    list(4);
+  }
+  __syncthreads();
+  for (int n = 0; n < nb; ++n) {
+    const int bf = n & 1;
+    build_values(bf, bf);
+    // the planes of this batch: each lane ORs its eight entries' masks,
+    // then the four lane groups (entries 0-7, 8-15, 16-23, 24-31) combine
+    int sh[8];
+    unsigned pm = 0;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      sh[e] = shifts[bf][e0 + e];
+      pm |= (unsigned)sh[e] >> 24;
+    }
+    pm |= __shfl_xor(pm, 16, 64);
+    pm |= __shfl_xor(pm, 32, 64);
+    const bool active = (pm >> z) & 1u;
+    // this wave's A tiles, into registers (the staged rows of this batch
+    // are overwritten two batches on)
+    uint4 ah[2], al[2];
+    if (active) {
+      float a0[8], a1[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int qe = e0 + e;
+        const float zx = wrow[bf][2][qe][((sh[e] >> 16) & 255) + z] *
+                         wrow[bf][0][qe][(sh[e] & 255) + fx];
+        const int yb = ((sh[e] >> 8) & 255) + fy;
+        a0[e] = zx * wrow[bf][1][qe][yb];
+        a1[e] = zx * wrow[bf][1][qe][yb + 2];
+      }
+      unsigned hi0[4], lo0[4], hi1[4], lo1[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        split2(a0[2 * e], a0[2 * e + 1], hi0[e], lo0[e]);
+        split2(a1[2 * e], a1[2 * e + 1], hi1[e], lo1[e]);
+      }
+      ah[0] = make_uint4(hi0[0], hi0[1], hi0[2], hi0[3]);
+      al[0] = make_uint4(lo0[0], lo0[1], lo0[2], lo0[3]);
+      ah[1] = make_uint4(hi1[0], hi1[1], hi1[2], hi1[3]);
+      al[1] = make_uint4(lo1[0], lo1[1], lo1[2], lo1[3]);
+    }
+    // the set of batch n + 1 stages it into the other buffer and loads
+    // batch n + 3 and the list of batch n + 5
+    if (set == ((n + 1) & 1) && n + 1 < nb) {
+      stage(bf ^ 1, n + 1);
+      if (n + 3 < nb) {
+        fetch(n + 3);
+        if (n + 5 < nb) list(n + 5);
+      }
+    }
+    __syncthreads();
+    if (active) {
+#pragma unroll
+      for (int c = 0; c < NCT; ++c) {
+        const sdn_half8 b_hi = __builtin_bit_cast(sdn_half8, sB[bf][c][0][lane]);
+        const sdn_half8 b_lo = __builtin_bit_cast(sdn_half8, sB[bf][c][1][lane]);
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          const sdn_half8 a_hi = __builtin_bit_cast(sdn_half8, ah[t]);
+          const sdn_half8 a_lo = __builtin_bit_cast(sdn_half8, al[t]);
+          acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a_hi, b_hi, acc[t][c], 0, 0, 0);
+          acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a_hi, b_lo, acc[t][c], 0, 0, 0);
+          acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a_lo, b_hi, acc[t][c], 0, 0, 0);
+        }
+      }
+    }
+  }
+  // lane holds rows 4 (lane / 16) + i of its row tiles t, i.e. cells
+  // (y, x) = (4 h + 2 t + (lane / 16) / 2, 4 ((lane / 16) & 1) + i), of
+  // column 16 c + lane % 16 = (coil, channel, re/im)
+  const float inv = 1.f / s;
+  const int qq = lane >> 4;
+  const int x0 = 4 * (qq & 1);
+#pragma unroll
+  for (int c = 0; c < NCT; ++c) {
+    const int col = 16 * c + r16;
+    const int gl = col / (2 * K), kk = (col >> 1) - gl * K, ri = col & 1;
+    if (gl >= G) continue;
+    const int g = g0 + gl;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int y = 4 * h + 2 * t + (qq >> 1);
+      if (it.w >= 0) {
+        float *pp = reinterpret_cast<float *>(
+            a.part + (((size_t)it.w * a.groups + g) * K + kk) * kSBCells + z * 64 + y * 8 + x0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) pp[2 * i + ri] = acc[t][c][i] * inv;
+      } else if (oz + z < a.nfz && oy + y < a.nfy) {
+        float *gp = reinterpret_cast<float *>(
+            a.grid + (size_t)(g * K + kk) * a.G + ((size_t)(oz + z) * a.nfy + oy + y) * a.nfx + ox + x0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (ox + x0 + i < a.nfx) gp[2 * i + ri] = acc[t][c][i] * inv;
+      }
+    }
+  }
+}
+
 // Largest |component| of n complex values, as float bits (non-negative
 // floats order like their bit patterns) into *out, which starts at zero.
 // Four 8-byte loads per thread are in flight per step.
@@ -1017,18 +1331,46 @@ hipError_t spread_mma(const SpreadDev &d, int K, dim3 grd, const unsigned *absma
   return hipGetLastError();
 }
 
+template <int W>
+hipError_t spread_pw(const SpreadDev &d, int K, dim3 grd, const unsigned *absmax, hipStream_t st) {
+  // a workgroup takes up to pw_coils(K) coils: 2 K value columns each, in
+  // 16-column tiles (5 tiles run as 6)
+  const int gmax = pw_coils(W, K);
+  const int G = std::min(d.groups, gmax);
+  int nct = (2 * K * G + 15) / 16;
+  if (nct == 5) nct = 6;
+  grd.y = (unsigned)((d.groups + gmax - 1) / gmax);
+  switch (K * 8 + nct) {
+#define SDN_SPW(KV, NV)                                                                   \
+  case KV * 8 + NV:                                                                       \
+    hipLaunchKernelGGL((k_spread_pw<W, KV, NV>), grd, dim3(64 * kPwWaves), 0, st, d, absmax); \
+    break;
+#define SDN_SPW5(KV) SDN_SPW(KV, 1) SDN_SPW(KV, 2) SDN_SPW(KV, 3) SDN_SPW(KV, 4) SDN_SPW(KV, 6)
+    SDN_SPW5(2) SDN_SPW5(3) SDN_SPW5(4) SDN_SPW5(5) SDN_SPW5(6) SDN_SPW5(7) SDN_SPW5(8)
+#undef SDN_SPW5
+#undef SDN_SPW
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 }  // namespace
 
-// The matrix-core spreading serves the subspace-mixing calls; it needs every
-// fine axis >= 16 cells (no support touches both ends of a block) and at
-// least two channels per coil.
-bool spread_engine_for(const sdn_plan_s &p, int K, int groups) {
-  if (p.spread_engine == SDN_SPREAD_GATHER) return false;
+// The matrix-core spreadings serve the subspace-mixing calls; they need
+// every fine axis >= 16 cells (no support touches both ends of a block) and
+// at least two channels per coil.
+int spread_engine_for(const sdn_plan_s &p, int K, int groups) {
+  if (p.spread_engine == SDN_SPREAD_GATHER) return SDN_SPREAD_GATHER;
+  const bool ok = K >= 2 && p.ax[0].nf >= 16 && p.ax[1].nf >= 16 && p.ax[2].nf >= 16 &&
+                  p.absmax != nullptr && (p.vinfo != nullptr || p.nvisit == 0);
+  if (!ok) return SDN_SPREAD_GATHER;
+  if (p.spread_engine != SDN_SPREAD_AUTO) return p.spread_engine;
   // automatic choice: the matrix cores pay once several coils share the
-  // point data of a block; a single coil group keeps the gather
-  if (p.spread_engine == SDN_SPREAD_AUTO && groups < 2) return false;
-  return K >= 2 && p.ax[0].nf >= 16 && p.ax[1].nf >= 16 && p.ax[2].nf >= 16 &&
-         p.absmax != nullptr && (p.vinfo != nullptr || p.nvisit == 0);
+  // point data of a block (a single coil keeps the gather); the plane split
+  // builds the value operand once for all coils and channels, which pays
+  // from about 32 of them
+  if (groups < 2) return SDN_SPREAD_GATHER;
+  return K * groups >= kPlanesFrom ? SDN_SPREAD_PLANES : SDN_SPREAD_MATRIX;
 }
 
 namespace {
@@ -1071,7 +1413,8 @@ hipError_t launch_spread(const sdn_plan_s &p, const SpreadArgs &a, hipStream_t s
   const bool mix = a.V != nullptr;
   dim3 grd((unsigned)p.nsitems, (unsigned)a.groups);
   hipError_t e;
-  if (mix && spread_engine_for(p, a.K, a.groups)) {
+  const int engine = mix ? spread_engine_for(p, a.K, a.groups) : SDN_SPREAD_GATHER;
+  if (engine != SDN_SPREAD_GATHER) {
     // value scale: the largest component of the residuals (unless the
     // interpolation that produced them recorded it) and of V
     if (a.src_max_ready) {
@@ -1086,10 +1429,18 @@ hipError_t launch_spread(const sdn_plan_s &p, const SpreadArgs &a, hipStream_t s
                        p.absmax + 1);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    switch (p.W) {
-      case 4: e = spread_mma<4, true>(d, a.K, grd, p.absmax, st); break;
-      case 8: e = spread_mma<8, true>(d, a.K, grd, p.absmax, st); break;
-      default: e = spread_mma<6, true>(d, a.K, grd, p.absmax, st); break;
+    if (engine == SDN_SPREAD_PLANES) {
+      switch (p.W) {
+        case 4: e = spread_pw<4>(d, a.K, grd, p.absmax, st); break;
+        case 8: e = spread_pw<8>(d, a.K, grd, p.absmax, st); break;
+        default: e = spread_pw<6>(d, a.K, grd, p.absmax, st); break;
+      }
+    } else {
+      switch (p.W) {
+        case 4: e = spread_mma<4, true>(d, a.K, grd, p.absmax, st); break;
+        case 8: e = spread_mma<8, true>(d, a.K, grd, p.absmax, st); break;
+        default: e = spread_mma<6, true>(d, a.K, grd, p.absmax, st); break;
+      }
     }
   } else {
     switch (p.W) {

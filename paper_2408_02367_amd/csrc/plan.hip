@@ -468,7 +468,7 @@ sdn_status sdn_plan_create(sdn_plan *out, const int64_t shape[3], const float *t
   p->ncoef = kernel_ncoef(o.W);
   kernel_coefficients(o.W, beta, p->ncoef, &p->coef);
   p->budget = o.workspace_budget;
-  if (o.spread_engine < SDN_SPREAD_AUTO || o.spread_engine > SDN_SPREAD_MATRIX)
+  if (o.spread_engine < SDN_SPREAD_AUTO || o.spread_engine > SDN_SPREAD_PLANES)
     return delete p, fail(SDN_E_INVALID, "sdn_plan_create: unknown spread_engine");
   p->spread_engine = o.spread_engine;
   if (o.point_order != SDN_ORDER_AUTO && o.point_order != SDN_ORDER_CELL)
@@ -825,8 +825,15 @@ sdn_status sdn_plan_get_info(sdn_plan p, sdn_plan_info *info) {
   info->nwork = p->nwork;
   info->max_bin = p->max_bin;
   info->nvisit = p->nvisit;
-  info->spread_engine = spread_engine_for(*p, 2, 2) ? SDN_SPREAD_MATRIX : SDN_SPREAD_GATHER;
+  info->spread_engine = spread_engine_for(*p, 2, 2);
   info->ncoef = p->ncoef;
+  return SDN_OK;
+}
+
+sdn_status sdn_spread_engine(sdn_plan p, int B, int K, int *engine) {
+  if (!p || p->magic != kPlanMagic) return fail(SDN_E_STATE, "sdn_spread_engine: not a live plan");
+  if (!engine || B < 1 || K < 1) return fail(SDN_E_INVALID, "sdn_spread_engine: bad argument");
+  *engine = spread_engine_for(*p, K, B);
   return SDN_OK;
 }
 

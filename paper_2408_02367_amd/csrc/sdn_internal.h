@@ -247,9 +247,12 @@ struct SpreadArgs {
                       // of src (written by the interpolation that produced it)
 };
 hipError_t launch_spread(const sdn_plan_s &p, const SpreadArgs &a, hipStream_t st);
-// True when a spreading call with K channels per group and `groups` groups
-// (coils) runs on the matrix cores.
-bool spread_engine_for(const sdn_plan_s &p, int K, int groups);
+// Engine (SDN_SPREAD_GATHER, _MATRIX or _PLANES) of a subspace-mixing
+// spreading call with K channels per group and `groups` groups (coils).
+int spread_engine_for(const sdn_plan_s &p, int K, int groups);
+// Automatic engine choice: the plane-split matrix spreading from this many
+// (coil, channel) pairs per call.
+constexpr int kPlanesFrom = 32;
 size_t spread_part_elems(const sdn_plan_s &p, int groups, int K);
 
 // Plain-path subspace mix kernels (user order).

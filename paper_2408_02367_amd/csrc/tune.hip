@@ -72,9 +72,12 @@ sdn_status sdn_autotune(const int64_t shape[3], const float *traj, int64_t M,
   std::vector<sdn_opts> cand;
   for (int tile : {0, 8, 16})
     for (int cap : {0, 1024})
-      for (int eng : {SDN_SPREAD_GATHER, SDN_SPREAD_MATRIX})
+      for (int eng : {SDN_SPREAD_GATHER, SDN_SPREAD_MATRIX, SDN_SPREAD_PLANES})
         for (int order : {SDN_ORDER_AUTO, SDN_ORDER_CELL}) {
-          if (eng == SDN_SPREAD_MATRIX && order == SDN_ORDER_CELL) continue;
+          if (eng != SDN_SPREAD_GATHER && order == SDN_ORDER_CELL) continue;
+          // one channel per coil always gathers: the matrix engines would
+          // only repeat the gather candidates
+          if (eng != SDN_SPREAD_GATHER && K < 2) continue;
           sdn_opts o = o0;
           o.tile = tile;
           o.max_points_per_item = cap;

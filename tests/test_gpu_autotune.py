@@ -18,7 +18,7 @@ def test_autotune_result_is_valid_and_cached(tmp_path):
     cache = str(tmp_path / "tune.json")
     best = sdn.autotune(to_gpu(traj), shape, B, K, frame_of_point=to_gpu(frame), T=T, cache=cache)
     assert best["tile"] in (0, 8, 16) and best["max_points_per_item"] in (0, 1024)
-    assert best["spread_engine"] in ("gather", "matrix") and best["ms"] > 0
+    assert best["spread_engine"] in ("gather", "matrix", "planes") and best["ms"] > 0
     assert best["point_order"] in ("auto", "cell")
     assert best["point_order"] == "auto" or best["spread_engine"] == "gather"
     assert sdn.autotune(to_gpu(traj), shape, B, K, frame_of_point=to_gpu(frame), T=T,

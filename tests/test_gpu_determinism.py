@@ -18,7 +18,7 @@ from gpu_common import c64, to_gpu
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("B,engine", [(4, "auto"), (1, "auto"), (3, "gather")])
+@pytest.mark.parametrize("B,engine", [(4, "auto"), (1, "auto"), (3, "gather"), (7, "planes")])
 def test_dc_step_is_bitwise_repeatable(B, engine):
     shape, K, C, T = (24, 20, 28), 5, 8, 9
     traj, frame = wl.spiral_trajectory(T, 6, 900)

@@ -77,10 +77,26 @@ def test_one_coil_cell_order(K):
 def test_gather_engine_forced_at_several_coils(K, B):
     c = _case(K, B, seed=45 + K)
     p = _plan(c, spread_engine="gather")
+    assert p.spread_engine(B, K) == "gather"
     _check_grad_and_adjoint(c, p)
-    # and it equals the matrix-core engine to the FP32 summation order
-    q = _plan(c, spread_engine="matrix")
+    # and it equals both matrix-core engines to the FP32 summation order
     r = c64(wl.random_kspace((B, c["traj"].shape[0]), 46))
     s, V = c64(c["smaps"]), c64(c["V"])
-    assert rel(host(sdn.mrf_adjoint(p, r, s, c["coil_idx"], V)),
-               host(sdn.mrf_adjoint(q, r, s, c["coil_idx"], V))) < 1e-6
+    ref = host(sdn.mrf_adjoint(p, r, s, c["coil_idx"], V))
+    for engine in ("matrix", "planes"):
+        q = _plan(c, spread_engine=engine)
+        assert q.spread_engine(B, K) == engine
+        assert rel(host(sdn.mrf_adjoint(q, r, s, c["coil_idx"], V)), ref) < 1e-6, engine
+
+
+@pytest.mark.parametrize("K,B", [(6, 8), (5, 4), (2, 3), (8, 7), (3, 20)])
+def test_plane_split_engine(K, B):
+    """The plane-split matrix spreading (the automatic choice from 32 coil-
+    channel pairs) against the oracle, at column tilings of 1 to 6 tiles
+    and several coil groups per block (K = 3, B = 20: two groups)."""
+    c = _case(K, B, C=max(B, 6), T=max(7, K + 2), seed=50 + K + B)
+    p = _plan(c, spread_engine="planes")
+    assert p.spread_engine(B, K) == "planes"
+    _check_grad_and_adjoint(c, p)
+    if K * B >= 32:
+        assert _plan(c).spread_engine(B, K) == "planes"

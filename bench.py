@@ -338,6 +338,17 @@ def measure(workload, a, steps, warmup, dev, torch, sdn, wl, headline):
             stages[st] = (m0 + ms, n0 + n)
         v["plan"].profile(False)
     out["eager_profiled_ms_per_step"] = round(eager_ms, 3)
+    if group is not None:
+        # the group call (one interpolation and one spreading launch over all
+        # volumes) against the member plans called one after another, both
+        # as eager calls
+        def loop_step():
+            for v in vols:
+                sdn.mrf_dc_grad(v["plan"], v["x"], v["smaps"], v["ci"], v["V"], v["d"],
+                                grad=v["grad"], loss=v["loss"])
+
+        out["ragged_fused_eager_ms"] = _timed(step, torch, reps=steps)
+        out["ragged_member_loop_eager_ms"] = _timed(loop_step, torch, reps=steps)
 
     # the plain per-coil/per-channel path on the same data, on plans built
     # with the options the autotuner finds fastest for one coil and channel

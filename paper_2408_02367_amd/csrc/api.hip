@@ -849,3 +849,161 @@ sdn_status sdn_mrf_dc_grad_noalloc(sdn_plan p, const void *x, int K, const void 
 }
 
 }  // extern "C"
+
+namespace sdn {
+
+// Ragged volumes as one launch per gridding stage: the per-volume passes
+// (forward x/y/z, inverse z/y/x) run volume by volume, the interpolation
+// and the spreading of all volumes each as one launch over their work
+// items.  Returns SDN_E_UNSUPPORTED (nothing enqueued) when the volumes
+// cannot share those launches: more than kMaxFusedPlans, different kernel
+// widths or spreading engines, an empty plan, or a minibatch that a
+// workspace budget would split into coil passes.  The fused stages are
+// timed on the first plan's stage events.
+namespace {
+
+sdn_status group_prepare(sdn_plan const *plans, int n, const void *const *x, int K,
+                         const void *const *smaps, const int *C, const int32_t *const *coil_idx,
+                         int B, const void *const *V, const void *const *k_arr, const char *fn,
+                         bool need_kbuf, bool need_part) {
+  if (n < 1 || n > kMaxFusedPlans) return SDN_E_UNSUPPORTED;
+  for (int v = 0; v < n; ++v) {
+    SDN_TRY(check_plan(plans[v], fn));
+    SDN_TRY(check_mrf_args(*plans[v], fn, x[v], K, smaps[v], C[v], coil_idx[v], B, V[v], k_arr[v]));
+  }
+  const int engine = spread_engine_for(*plans[0], K, B);
+  for (int v = 0; v < n; ++v) {
+    const sdn_plan_s &p = *plans[v];
+    int per = 0;
+    if (p.M == 0 || p.W != plans[0]->W || spread_engine_for(p, K, B) != engine ||
+        channels_per_pass(p, K, B, &per, fn) != SDN_OK || per < B)
+      return SDN_E_UNSUPPORTED;
+  }
+  for (int v = 0; v < n; ++v) {
+    sdn_plan_s *p = plans[v];
+    SDN_TRY(ensure_grid(p, (size_t)B * K * fine_cells(*p)));
+    if (need_kbuf) SDN_TRY(ensure_kbuf(p, (size_t)B * p->M));
+    if (need_kbuf) SDN_TRY(ensure_lpart(p, B));
+    if (need_part) SDN_TRY(ensure_part(p, B, K));
+  }
+  return SDN_OK;
+}
+
+}  // namespace
+
+sdn_status group_dc_grad_fused(sdn_plan const *plans, int n, const void *const *x, int K,
+                               const void *const *smaps, const int *C,
+                               const int32_t *const *coil_idx, int B, const void *const *V,
+                               const void *const *d, const float *const *w, double *losses,
+                               void *const *grad, void *stream) {
+  SDN_TRY(group_prepare(plans, n, x, K, smaps, C, coil_idx, B, V, d, "sdn_group_mrf_dc_grad",
+                        true, true));
+  hipStream_t st = (hipStream_t)stream;
+  sdn_plan_s *p0 = plans[0];
+  InterpArgs ia[kMaxFusedPlans];
+  SpreadArgs sa[kMaxFusedPlans];
+  const sdn_plan_s *cp[kMaxFusedPlans];
+  for (int v = 0; v < n; ++v) {
+    sdn_plan_s *p = plans[v];
+    cp[v] = p;
+    SDN_HIP(launch_fill_zero_f64(losses + v, 1, st), "loss clear");
+    SDN_TRY(forward_grid(p, (const float2 *)x[v], K, (const float2 *)smaps[v],
+                         coil_list(coil_idx[v], 0, B), B, p->grid, st));
+    InterpArgs &a = ia[v];
+    a = InterpArgs{};
+    a.grid = p->grid;
+    a.P = B * K;
+    a.groups = B;
+    a.kg = K;
+    a.V = (const float2 *)V[v];
+    a.dc = 1;
+    a.rscale = 2.f;
+    a.d = (const float2 *)d[v];
+    a.w = w ? w[v] : nullptr;
+    a.r_plan = p->kbuf;
+    a.loss = losses + v;
+    a.loss_part = p->lpart;
+    a.rmax = p->absmax;
+    SpreadArgs &b = sa[v];
+    b = SpreadArgs{};
+    b.grid = p->grid;
+    b.part = p->part;
+    b.groups = B;
+    b.K = K;
+    b.V = (const float2 *)V[v];
+    b.src = p->kbuf;
+    b.src_plan_order = true;
+    b.src_max_ready = true;
+  }
+  {
+    sdn_plan_s *p = p0;
+    SDN_STAGE(p, SDN_STAGE_INTERP, launch_interp_fused(cp, ia, n, st), "fused interpolation + residual");
+    SDN_STAGE(p, SDN_STAGE_SPREAD, launch_spread_fused(cp, sa, n, st), "fused spreading");
+  }
+  for (int v = 0; v < n; ++v)
+    SDN_TRY(adjoint_grid(plans[v], K, (const float2 *)smaps[v], coil_list(coil_idx[v], 0, B), B,
+                         (float2 *)grad[v], 0, plans[v]->grid, st));
+  return SDN_OK;
+}
+
+sdn_status group_forward_fused(sdn_plan const *plans, int n, const void *const *x, int K,
+                               const void *const *smaps, const int *C,
+                               const int32_t *const *coil_idx, int B, const void *const *V,
+                               void *const *y, void *stream) {
+  SDN_TRY(group_prepare(plans, n, x, K, smaps, C, coil_idx, B, V, (const void *const *)y,
+                        "sdn_group_mrf_forward", false, false));
+  hipStream_t st = (hipStream_t)stream;
+  InterpArgs ia[kMaxFusedPlans];
+  const sdn_plan_s *cp[kMaxFusedPlans];
+  for (int v = 0; v < n; ++v) {
+    sdn_plan_s *p = plans[v];
+    cp[v] = p;
+    SDN_TRY(forward_grid(p, (const float2 *)x[v], K, (const float2 *)smaps[v],
+                         coil_list(coil_idx[v], 0, B), B, p->grid, st));
+    InterpArgs &a = ia[v];
+    a = InterpArgs{};
+    a.grid = p->grid;
+    a.P = B * K;
+    a.groups = B;
+    a.kg = K;
+    a.V = (const float2 *)V[v];
+    a.y = (float2 *)y[v];
+  }
+  sdn_plan_s *p = plans[0];
+  SDN_STAGE(p, SDN_STAGE_INTERP, launch_interp_fused(cp, ia, n, st), "fused interpolation");
+  return SDN_OK;
+}
+
+sdn_status group_adjoint_fused(sdn_plan const *plans, int n, const void *const *y, int K,
+                               const void *const *smaps, const int *C,
+                               const int32_t *const *coil_idx, int B, const void *const *V,
+                               void *const *x_out, int accumulate, void *stream) {
+  SDN_TRY(group_prepare(plans, n, (const void *const *)x_out, K, smaps, C, coil_idx, B, V, y,
+                        "sdn_group_mrf_adjoint", false, true));
+  hipStream_t st = (hipStream_t)stream;
+  SpreadArgs sa[kMaxFusedPlans];
+  const sdn_plan_s *cp[kMaxFusedPlans];
+  for (int v = 0; v < n; ++v) {
+    sdn_plan_s *p = plans[v];
+    cp[v] = p;
+    SpreadArgs &b = sa[v];
+    b = SpreadArgs{};
+    b.grid = p->grid;
+    b.part = p->part;
+    b.groups = B;
+    b.K = K;
+    b.V = (const float2 *)V[v];
+    b.src = (const float2 *)y[v];
+    b.src_plan_order = false;
+  }
+  {
+    sdn_plan_s *p = plans[0];
+    SDN_STAGE(p, SDN_STAGE_SPREAD, launch_spread_fused(cp, sa, n, st), "fused spreading");
+  }
+  for (int v = 0; v < n; ++v)
+    SDN_TRY(adjoint_grid(plans[v], K, (const float2 *)smaps[v], coil_list(coil_idx[v], 0, B), B,
+                         (float2 *)x_out[v], accumulate, plans[v]->grid, st));
+  return SDN_OK;
+}
+
+}  // namespace sdn

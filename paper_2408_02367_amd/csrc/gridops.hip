@@ -54,6 +54,25 @@ TileGeom tile_geom(const sdn_plan_s &p) {
   return g;
 }
 
+// Ragged volumes: one launch over the work items of several plans.  The
+// workgroups of volume v are start[v] .. start[v+1]-1 of the grid's x
+// dimension; each reads its volume's descriptor.
+constexpr int kMaxFused = kMaxFusedPlans;
+template <typename Dev>
+struct Fused {
+  int n;
+  int start[kMaxFused + 1];
+  Dev dev[kMaxFused];
+};
+
+template <typename Dev>
+__device__ __forceinline__ int fused_volume(const Fused<Dev> &f, int &item) {
+  int v = 0;
+  while (v + 1 < f.n && (int)blockIdx.x >= f.start[v + 1]) ++v;
+  item = (int)blockIdx.x - f.start[v];
+  return v;
+}
+
 struct InterpDev {
   const float4 *rec;
   const int2 *pidx;
@@ -74,6 +93,7 @@ struct InterpDev {
   double *loss_part;   // DC mode: one partial loss per workgroup, [groups][items]
   float rscale;
   unsigned *rmax;
+  int nitems;          // work items of this plan (the loss partials' row length)
 };
 
 constexpr int kThreads = 256;
@@ -88,14 +108,69 @@ constexpr int kIThreads = 512;                // interpolation workgroup
 // serves an 8-byte LDS read to 32 lanes at a time from 64 banks, so each
 // half-wave's reads then hit distinct banks, or share a read, at every one
 // of the W^3 offsets.
+// End of a mixing interpolation item: the points' mixed sums acc[i] (point
+// tid + i kIThreads of item wi) to y in user order, or in DC mode the
+// residuals in plan order and the workgroup's partial loss and largest
+// residual component.
+template <bool DC, int NP>
+__device__ __forceinline__ void interp_epilogue(const InterpDev &a, const int4 &wi, int grp, int tid,
+                                                float2 (&acc)[NP], int item) {
+  constexpr int kPts = NP;
+  double my_loss = 0.0;
+  float my_max = 0.f;
+#pragma unroll
+  for (int i = 0; i < kPts; ++i) {
+    const int q = tid + i * kIThreads;
+    if (q >= wi.z) break;
+    const int orig = a.pidx[wi.y + q].y;
+    if constexpr (DC) {
+      const float2 dv = a.d ? a.d[(size_t)grp * a.M + orig] : make_float2(0.f, 0.f);
+      const float2 df = csub(acc[i], dv);
+      const float wt = a.w ? a.w[orig] : 1.f;
+      my_loss += (double)wt * ((double)df.x * df.x + (double)df.y * df.y);
+      const float sw = a.rscale * wt;
+      const float2 rv = make_float2(sw * df.x, sw * df.y);
+      my_max = fmaxf(my_max, fmaxf(fabsf(rv.x), fabsf(rv.y)));
+      a.r_plan[(size_t)(wi.y + q) * gridDim.y + grp] = rv;
+    } else {
+      a.y[(size_t)grp * a.M + orig] = acc[i];
+    }
+  }
+  if constexpr (DC) {
+    __shared__ double part[kIThreads / 64];
+    __shared__ float pmax[kIThreads / 64];
+    for (int off = 32; off > 0; off >>= 1) {
+      my_loss += __shfl_down(my_loss, off, 64);
+      my_max = fmaxf(my_max, __shfl_xor(my_max, off, 64));
+    }
+    if ((tid & 63) == 0) {
+      part[tid >> 6] = my_loss;
+      pmax[tid >> 6] = my_max;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double s = 0.0;
+      float mx = 0.f;
+      for (int i = 0; i < kIThreads / 64; ++i) {
+        s += part[i];
+        mx = fmaxf(mx, pmax[i]);
+      }
+      if (a.rmax) atomicMax(a.rmax, __float_as_uint(mx));
+      // the partials are summed afterwards in a fixed order, so the loss
+      // does not depend on the order in which workgroups finish
+      a.loss_part[(size_t)blockIdx.y * a.nitems + item] = s;
+    }
+  }
+}
+
 template <int W, bool MIX, bool DC, bool BUF>
-__global__ void __launch_bounds__(kIThreads) k_interp(InterpDev a) {
+__device__ __forceinline__ void interp_body(const InterpDev &a, int item) {
   extern __shared__ float2 tile[];
   // raw buffer over the transposed records (word 3: the gfx9 raw-buffer format)
   const __amdgpu_buffer_rsrc_t wrsrc = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<float *>(a.wts_t), 0, (int)a.rec_bytes, 0x00020000);
   const TileGeom &g = a.g;
-  const int4 wi = a.work[blockIdx.x];
+  const int4 wi = a.work[item];
   const int grp = blockIdx.y;
   const int tid = threadIdx.x;
   const int tz = wi.x / (g.ntx * g.nty);
@@ -210,53 +285,19 @@ __global__ void __launch_bounds__(kIThreads) k_interp(InterpDev a) {
     }
     __syncthreads();
   }
-  if constexpr (MIX) {
-    double my_loss = 0.0;
-    float my_max = 0.f;
-#pragma unroll
-    for (int i = 0; i < kPts; ++i) {
-      const int q = tid + i * kIThreads;
-      if (q >= wi.z) break;
-      const int orig = a.pidx[wi.y + q].y;
-      if constexpr (DC) {
-        const float2 dv = a.d ? a.d[(size_t)grp * a.M + orig] : make_float2(0.f, 0.f);
-        const float2 df = csub(acc[i], dv);
-        const float wt = a.w ? a.w[orig] : 1.f;
-        my_loss += (double)wt * ((double)df.x * df.x + (double)df.y * df.y);
-        const float sw = a.rscale * wt;
-        const float2 rv = make_float2(sw * df.x, sw * df.y);
-        my_max = fmaxf(my_max, fmaxf(fabsf(rv.x), fabsf(rv.y)));
-        a.r_plan[(size_t)(wi.y + q) * gridDim.y + grp] = rv;
-      } else {
-        a.y[(size_t)grp * a.M + orig] = acc[i];
-      }
-    }
-    if constexpr (DC) {
-      __shared__ double part[kIThreads / 64];
-      __shared__ float pmax[kIThreads / 64];
-      for (int off = 32; off > 0; off >>= 1) {
-        my_loss += __shfl_down(my_loss, off, 64);
-        my_max = fmaxf(my_max, __shfl_xor(my_max, off, 64));
-      }
-      if ((tid & 63) == 0) {
-        part[tid >> 6] = my_loss;
-        pmax[tid >> 6] = my_max;
-      }
-      __syncthreads();
-      if (tid == 0) {
-        double s = 0.0;
-        float mx = 0.f;
-        for (int i = 0; i < kIThreads / 64; ++i) {
-          s += part[i];
-          mx = fmaxf(mx, pmax[i]);
-        }
-        if (a.rmax) atomicMax(a.rmax, __float_as_uint(mx));
-        // the partials are summed afterwards in a fixed order, so the loss
-        // does not depend on the order in which workgroups finish
-        a.loss_part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
-      }
-    }
-  }
+  if constexpr (MIX) interp_epilogue<DC>(a, wi, grp, tid, acc, item);
+}
+
+template <int W, bool MIX, bool DC, bool BUF>
+__global__ void __launch_bounds__(kIThreads) k_interp(InterpDev a) {
+  interp_body<W, MIX, DC, BUF>(a, (int)blockIdx.x);
+}
+
+template <int W, bool MIX, bool DC, bool BUF>
+__global__ void __launch_bounds__(kIThreads) k_interp_fused(Fused<InterpDev> f) {
+  int item;
+  const int v = fused_volume(f, item);
+  interp_body<W, MIX, DC, BUF>(f.dev[v], item);
 }
 
 struct SpreadDev {
@@ -276,6 +317,7 @@ struct SpreadDev {
   const float2 *V;
   const float2 *src;   // mix: [groups][M]; else [groups * K][M]
   int src_plan;
+  const unsigned *absmax;  // matrix engines: largest input magnitudes (value scale)
 };
 
 constexpr int kSB = kSpreadBlock;           // 8
@@ -346,13 +388,13 @@ __device__ __forceinline__ void pull_run(const float *bf, int v0, int v1, int l0
 }
 
 template <int W, bool MIX, int K>
-__global__ void __launch_bounds__(64) k_spread(SpreadDev a) {
+__device__ __forceinline__ void spread_gather_body(const SpreadDev &a, int item) {
   static_assert(W <= 8 && kSB == 8 && kVisitOffsets == 16, "offset cases cover -7 .. 7");
   using R = PullRec<W, K>;
   constexpr int RS = R::stride;
   __shared__ float4 batch[64 * RS / 4];
   float *bf = reinterpret_cast<float *>(batch);
-  const int4 it = a.items[blockIdx.x];
+  const int4 it = a.items[item];
   const int grp = blockIdx.y;
   const int lane = threadIdx.x;
   const int bzi = it.x / (a.nbx * a.nby);
@@ -448,6 +490,18 @@ __global__ void __launch_bounds__(64) k_spread(SpreadDev a) {
       if (oz + c < a.nfz)
         gp[((size_t)(oz + c) * a.nfy + gy) * a.nfx + gx] = make_float2(ar[c][kk], ai[c][kk]);
   }
+}
+
+template <int W, bool MIX, int K>
+__global__ void __launch_bounds__(64) k_spread(SpreadDev a) {
+  spread_gather_body<W, MIX, K>(a, (int)blockIdx.x);
+}
+
+template <int W, bool MIX, int K>
+__global__ void __launch_bounds__(64) k_spread_fused(Fused<SpreadDev> f) {
+  int item;
+  const int v = fused_volume(f, item);
+  spread_gather_body<W, MIX, K>(f.dev[v], item);
 }
 
 // ---------------------------------------------------------------------------
@@ -585,7 +639,8 @@ __device__ __forceinline__ void mma_fetch(const SpreadDev &a, const MmaList &L, 
 }
 
 template <int W, bool MIX, int K, int NG>
-__global__ void __launch_bounds__(64 * NG) k_spread_mma(SpreadDev a, const unsigned *absmax) {
+__device__ __forceinline__ void spread_mma_body(const SpreadDev &a, int item) {
+  const unsigned *absmax = a.absmax;
   // values per entry and coil: [re/im][k], K padded to even so that a lane
   // reads its component's K values with 8-byte loads
   constexpr int KP = (K + 1) & ~1;
@@ -597,7 +652,7 @@ __global__ void __launch_bounds__(64 * NG) k_spread_mma(SpreadDev a, const unsig
   __shared__ float2 rsd[2][NG][kMmaBatch];                    // mixing: each coil's residual
   __shared__ int shifts[2][kMmaBatch];
   __shared__ uint4 sA[2][2][4][64];   // [buffer][hi/lo][row tile][lane]: (y,x) operand fragments
-  const int4 it = a.items[blockIdx.x];
+  const int4 it = a.items[item];
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
   const int grp = blockIdx.y * NG + wv;
   const bool coil_ok = grp < a.groups;
@@ -795,6 +850,18 @@ __global__ void __launch_bounds__(64 * NG) k_spread_mma(SpreadDev a, const unsig
   }
 }
 
+template <int W, bool MIX, int K, int NG>
+__global__ void __launch_bounds__(64 * NG) k_spread_mma(SpreadDev a) {
+  spread_mma_body<W, MIX, K, NG>(a, (int)blockIdx.x);
+}
+
+template <int W, bool MIX, int K, int NG>
+__global__ void __launch_bounds__(64 * NG) k_spread_mma_fused(Fused<SpreadDev> f) {
+  int item;
+  const int v = fused_volume(f, item);
+  spread_mma_body<W, MIX, K, NG>(f.dev[v], item);
+}
+
 // ---------------------------------------------------------------------------
 // Spreading as a matrix product, split by planes (many coils and channels).
 //
@@ -846,7 +913,8 @@ struct PwList {
 };
 
 template <int W, int K, int NCT>
-__global__ void __launch_bounds__(64 * kPwWaves) k_spread_pw(SpreadDev a, const unsigned *absmax) {
+__device__ __forceinline__ void spread_pw_body(const SpreadDev &a, int item) {
+  const unsigned *absmax = a.absmax;
   constexpr int GMAX = pw_coils(W, K);        // coils of a full workgroup
   constexpr int NVP = (K + 1) / 2;            // basis pieces per entry
   constexpr int NRP = (GMAX + 1) / 2;         // residual pieces per entry
@@ -861,7 +929,7 @@ __global__ void __launch_bounds__(64 * kPwWaves) k_spread_pw(SpreadDev a, const 
   __shared__ float2 rsd[2][kMmaBatch][2 * NRP];
   __shared__ uint4 sB[2][NCT][2][64];         // [buffer][column tile][hi/lo][lane]
 
-  const int4 it = a.items[blockIdx.x];
+  const int4 it = a.items[item];
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
   const int g0 = blockIdx.y * GMAX;
   const int G = min(GMAX, a.groups - g0);     // coils of this workgroup
@@ -1109,6 +1177,18 @@ __global__ void __launch_bounds__(64 * kPwWaves) k_spread_pw(SpreadDev a, const 
   }
 }
 
+template <int W, int K, int NCT>
+__global__ void __launch_bounds__(64 * kPwWaves) k_spread_pw(SpreadDev a) {
+  spread_pw_body<W, K, NCT>(a, (int)blockIdx.x);
+}
+
+template <int W, int K, int NCT>
+__global__ void __launch_bounds__(64 * kPwWaves) k_spread_pw_fused(Fused<SpreadDev> f) {
+  int item;
+  const int v = fused_volume(f, item);
+  spread_pw_body<W, K, NCT>(f.dev[v], item);
+}
+
 // Largest |component| of n complex values, as float bits (non-negative
 // floats order like their bit patterns) into *out, which starts at zero.
 // Four 8-byte loads per thread are in flight per step.
@@ -1207,26 +1287,34 @@ template <typename F>
 hipError_t allow_lds_fwd(F *kernel, size_t bytes);
 
 template <int W, bool MIX, bool DC, bool BUF>
-hipError_t interp_one(const InterpDev &d, dim3 grd, size_t lds, hipStream_t st) {
-  hipError_t e = allow_lds_fwd(k_interp<W, MIX, DC, BUF>, lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_interp<W, MIX, DC, BUF>), grd, dim3(kIThreads), lds, st, d);
+hipError_t interp_one(const InterpDev &d, const Fused<InterpDev> *fz, dim3 grd, size_t lds,
+                      hipStream_t st) {
+  if (fz) {
+    hipError_t e = allow_lds_fwd(k_interp_fused<W, MIX, DC, BUF>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_interp_fused<W, MIX, DC, BUF>), grd, dim3(kIThreads), lds, st, *fz);
+  } else {
+    hipError_t e = allow_lds_fwd(k_interp<W, MIX, DC, BUF>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_interp<W, MIX, DC, BUF>), grd, dim3(kIThreads), lds, st, d);
+  }
   return hipGetLastError();
 }
 
 template <int W, bool BUF>
-hipError_t interp_launch_b(const InterpDev &d, bool mix, bool dc, dim3 grd, size_t lds,
-                           hipStream_t st) {
-  if (mix && dc) return interp_one<W, true, true, BUF>(d, grd, lds, st);
-  if (mix) return interp_one<W, true, false, BUF>(d, grd, lds, st);
-  return interp_one<W, false, false, BUF>(d, grd, lds, st);
+hipError_t interp_launch_b(const InterpDev &d, const Fused<InterpDev> *fz, bool mix, bool dc,
+                           dim3 grd, size_t lds, hipStream_t st) {
+  if (mix && dc) return interp_one<W, true, true, BUF>(d, fz, grd, lds, st);
+  if (mix) return interp_one<W, true, false, BUF>(d, fz, grd, lds, st);
+  return interp_one<W, false, false, BUF>(d, fz, grd, lds, st);
 }
 
+// buf: every plan's transposed records are under 2 GiB (raw buffer loads)
 template <int W>
-hipError_t interp_launch(const InterpDev &d, bool mix, bool dc, dim3 grd, size_t lds,
-                         hipStream_t st) {
-  return d.rec_bytes ? interp_launch_b<W, true>(d, mix, dc, grd, lds, st)
-                     : interp_launch_b<W, false>(d, mix, dc, grd, lds, st);
+hipError_t interp_launch(const InterpDev &d, const Fused<InterpDev> *fz, bool buf, bool mix,
+                         bool dc, dim3 grd, size_t lds, hipStream_t st) {
+  return buf ? interp_launch_b<W, true>(d, fz, mix, dc, grd, lds, st)
+             : interp_launch_b<W, false>(d, fz, mix, dc, grd, lds, st);
 }
 
 }  // namespace
@@ -1260,8 +1348,10 @@ hipError_t allow_lds_fwd(F *kernel, size_t bytes) {
 }
 }  // namespace
 
-hipError_t launch_interp(const sdn_plan_s &p, const InterpArgs &a, hipStream_t st) {
-  if (p.M == 0 || p.nwork == 0) return hipSuccess;
+namespace {
+
+// Descriptor of one plan's interpolation call.
+InterpDev interp_dev(const sdn_plan_s &p, const InterpArgs &a) {
   InterpDev d;
   d.rec = p.rec;
   d.pidx = p.pidx;
@@ -1285,24 +1375,77 @@ hipError_t launch_interp(const sdn_plan_s &p, const InterpArgs &a, hipStream_t s
   d.loss_part = a.loss_part;
   d.rscale = a.rscale;
   d.rmax = a.dc ? a.rmax : nullptr;
+  d.nitems = (int)p.nwork;
+  return d;
+}
+
+bool interp_args_ok(const sdn_plan_s &p, const InterpArgs &a) {
+  const bool mix = a.V != nullptr;
+  if (a.dc && (!mix || a.r_plan == nullptr || a.loss == nullptr || a.loss_part == nullptr))
+    return false;
+  return interp_lds_bytes(p) <= max_lds_bytes();
+}
+
+// loss += the workgroups' partials, two fixed-order levels
+hipError_t interp_loss_sum(const sdn_plan_s &p, const InterpArgs &a, hipStream_t st) {
+  const size_t nparts = interp_loss_parts(p, a.groups);
+  return launch_sum(a.loss_part, (int)nparts, 1.0, a.loss, st, a.loss_part + nparts, true);
+}
+
+}  // namespace
+
+hipError_t launch_interp(const sdn_plan_s &p, const InterpArgs &a, hipStream_t st) {
+  if (p.M == 0 || p.nwork == 0) return hipSuccess;
+  if (!interp_args_ok(p, a)) return hipErrorInvalidValue;
+  const InterpDev d = interp_dev(p, a);
   const bool mix = a.V != nullptr;
   const bool dc = a.dc != 0;
-  if (dc && (!mix || a.r_plan == nullptr || a.loss == nullptr || a.loss_part == nullptr))
-    return hipErrorInvalidValue;
   const size_t lds = interp_lds_bytes(p);
-  if (lds > max_lds_bytes()) return hipErrorInvalidValue;
   if (d.rmax) hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, d.rmax, 1);
   dim3 grd((unsigned)p.nwork, (unsigned)a.groups);
   hipError_t e;
   switch (p.W) {
-    case 4: e = interp_launch<4>(d, mix, dc, grd, lds, st); break;
-    case 8: e = interp_launch<8>(d, mix, dc, grd, lds, st); break;
-    default: e = interp_launch<6>(d, mix, dc, grd, lds, st); break;
+    case 4: e = interp_launch<4>(d, nullptr, d.rec_bytes != 0, mix, dc, grd, lds, st); break;
+    case 8: e = interp_launch<8>(d, nullptr, d.rec_bytes != 0, mix, dc, grd, lds, st); break;
+    default: e = interp_launch<6>(d, nullptr, d.rec_bytes != 0, mix, dc, grd, lds, st); break;
   }
   if (e != hipSuccess || !dc) return e;
-  // loss += the workgroups' partials, two fixed-order levels
-  const size_t nparts = interp_loss_parts(p, a.groups);
-  return launch_sum(a.loss_part, (int)nparts, 1.0, a.loss, st, a.loss_part + nparts, true);
+  return interp_loss_sum(p, a, st);
+}
+
+hipError_t launch_interp_fused(const sdn_plan_s *const *plans, const InterpArgs *args, int n,
+                               hipStream_t st) {
+  if (n < 1 || n > kMaxFused) return hipErrorInvalidValue;
+  Fused<InterpDev> f{};
+  f.n = n;
+  size_t lds = 0;
+  bool buf = true;
+  int total = 0;
+  const bool mix = args[0].V != nullptr, dc = args[0].dc != 0;
+  for (int v = 0; v < n; ++v) {
+    const sdn_plan_s &p = *plans[v];
+    const InterpArgs &a = args[v];
+    if (p.M == 0 || p.nwork == 0 || p.W != plans[0]->W || a.groups != args[0].groups ||
+        (a.V != nullptr) != mix || (a.dc != 0) != dc || a.kg != args[0].kg || !interp_args_ok(p, a))
+      return hipErrorInvalidValue;
+    f.dev[v] = interp_dev(p, a);
+    buf = buf && f.dev[v].rec_bytes != 0;
+    lds = std::max(lds, interp_lds_bytes(p));
+    f.start[v] = total;
+    total += (int)p.nwork;
+    if (f.dev[v].rmax) hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, f.dev[v].rmax, 1);
+  }
+  f.start[n] = total;
+  dim3 grd((unsigned)total, (unsigned)args[0].groups);
+  hipError_t e;
+  switch (plans[0]->W) {
+    case 4: e = interp_launch<4>(f.dev[0], &f, buf, mix, dc, grd, lds, st); break;
+    case 8: e = interp_launch<8>(f.dev[0], &f, buf, mix, dc, grd, lds, st); break;
+    default: e = interp_launch<6>(f.dev[0], &f, buf, mix, dc, grd, lds, st); break;
+  }
+  if (e != hipSuccess || !dc) return e;
+  for (int v = 0; v < n && e == hipSuccess; ++v) e = interp_loss_sum(*plans[v], args[v], st);
+  return e;
 }
 
 size_t interp_loss_parts(const sdn_plan_s &p, int groups) { return (size_t)p.nwork * groups; }
@@ -1313,14 +1456,18 @@ size_t spread_part_elems(const sdn_plan_s &p, int groups, int K) {
 
 namespace {
 template <int W, bool MIX>
-hipError_t spread_mma(const SpreadDev &d, int K, dim3 grd, const unsigned *absmax, hipStream_t st) {
+hipError_t spread_mma(const SpreadDev &d, const Fused<SpreadDev> *fz, int K, dim3 grd,
+                      hipStream_t st) {
   // up to four coils per workgroup, one wave each
   const int ng = std::min(d.groups, 4);
   grd.y = (unsigned)((d.groups + ng - 1) / ng);
   switch (K * 8 + ng) {
-#define SDN_SPM(KV, NGV)                                                                 \
-  case KV * 8 + NGV:                                                                     \
-    hipLaunchKernelGGL((k_spread_mma<W, MIX, KV, NGV>), grd, dim3(64 * NGV), 0, st, d, absmax); \
+#define SDN_SPM(KV, NGV)                                                                    \
+  case KV * 8 + NGV:                                                                        \
+    if (fz)                                                                                 \
+      hipLaunchKernelGGL((k_spread_mma_fused<W, MIX, KV, NGV>), grd, dim3(64 * NGV), 0, st, *fz); \
+    else                                                                                    \
+      hipLaunchKernelGGL((k_spread_mma<W, MIX, KV, NGV>), grd, dim3(64 * NGV), 0, st, d);   \
     break;
 #define SDN_SPM4(KV) SDN_SPM(KV, 1) SDN_SPM(KV, 2) SDN_SPM(KV, 3) SDN_SPM(KV, 4)
     SDN_SPM4(2) SDN_SPM4(3) SDN_SPM4(4) SDN_SPM4(5) SDN_SPM4(6) SDN_SPM4(7) SDN_SPM4(8)
@@ -1332,7 +1479,8 @@ hipError_t spread_mma(const SpreadDev &d, int K, dim3 grd, const unsigned *absma
 }
 
 template <int W>
-hipError_t spread_pw(const SpreadDev &d, int K, dim3 grd, const unsigned *absmax, hipStream_t st) {
+hipError_t spread_pw(const SpreadDev &d, const Fused<SpreadDev> *fz, int K, dim3 grd,
+                     hipStream_t st) {
   // a workgroup takes up to pw_coils(K) coils: 2 K value columns each, in
   // 16-column tiles (5 tiles run as 6)
   const int gmax = pw_coils(W, K);
@@ -1341,9 +1489,12 @@ hipError_t spread_pw(const SpreadDev &d, int K, dim3 grd, const unsigned *absmax
   if (nct == 5) nct = 6;
   grd.y = (unsigned)((d.groups + gmax - 1) / gmax);
   switch (K * 8 + nct) {
-#define SDN_SPW(KV, NV)                                                                   \
-  case KV * 8 + NV:                                                                       \
-    hipLaunchKernelGGL((k_spread_pw<W, KV, NV>), grd, dim3(64 * kPwWaves), 0, st, d, absmax); \
+#define SDN_SPW(KV, NV)                                                                         \
+  case KV * 8 + NV:                                                                             \
+    if (fz)                                                                                     \
+      hipLaunchKernelGGL((k_spread_pw_fused<W, KV, NV>), grd, dim3(64 * kPwWaves), 0, st, *fz); \
+    else                                                                                        \
+      hipLaunchKernelGGL((k_spread_pw<W, KV, NV>), grd, dim3(64 * kPwWaves), 0, st, d);         \
     break;
 #define SDN_SPW5(KV) SDN_SPW(KV, 1) SDN_SPW(KV, 2) SDN_SPW(KV, 3) SDN_SPW(KV, 4) SDN_SPW(KV, 6)
     SDN_SPW5(2) SDN_SPW5(3) SDN_SPW5(4) SDN_SPW5(5) SDN_SPW5(6) SDN_SPW5(7) SDN_SPW5(8)
@@ -1376,23 +1527,25 @@ int spread_engine_for(const sdn_plan_s &p, int K, int groups) {
 namespace {
 
 template <int W, bool MIX>
-hipError_t spread_k(const SpreadDev &d, int K, dim3 grd, hipStream_t st) {
+hipError_t spread_k(const SpreadDev &d, const Fused<SpreadDev> *fz, int K, dim3 grd,
+                    hipStream_t st) {
   switch (K) {
-#define SDN_SPK(KV) \
-  case KV: hipLaunchKernelGGL((k_spread<W, MIX, KV>), grd, dim3(64), 0, st, d); break;
+#define SDN_SPK(KV)                                                                     \
+  case KV:                                                                              \
+    if (fz)                                                                             \
+      hipLaunchKernelGGL((k_spread_fused<W, MIX, KV>), grd, dim3(64), 0, st, *fz);      \
+    else                                                                                \
+      hipLaunchKernelGGL((k_spread<W, MIX, KV>), grd, dim3(64), 0, st, d);              \
+    break;
     SDN_SPK(1) SDN_SPK(2) SDN_SPK(3) SDN_SPK(4) SDN_SPK(5) SDN_SPK(6) SDN_SPK(7) SDN_SPK(8)
 #undef SDN_SPK
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
-}  // namespace
 
-hipError_t launch_spread(const sdn_plan_s &p, const SpreadArgs &a, hipStream_t st) {
-  if (p.M == 0 || p.sitems == nullptr) return hipErrorInvalidValue;
-  if (a.src_plan_order && a.V == nullptr) return hipErrorInvalidValue;
-  if (p.nslots > 0 && a.part == nullptr) return hipErrorInvalidValue;
-  if (a.K < 1 || a.K > kMaxK) return hipErrorInvalidValue;
+// Descriptor of one plan's spreading call.
+SpreadDev spread_dev(const sdn_plan_s &p, const SpreadArgs &a) {
   SpreadDev d;
   d.items = p.sitems;
   d.vlist = p.vlist;
@@ -1410,49 +1563,106 @@ hipError_t launch_spread(const sdn_plan_s &p, const SpreadArgs &a, hipStream_t s
   d.V = a.V;
   d.src = a.src;
   d.src_plan = a.src_plan_order ? 1 : 0;
-  const bool mix = a.V != nullptr;
-  dim3 grd((unsigned)p.nsitems, (unsigned)a.groups);
-  hipError_t e;
-  const int engine = mix ? spread_engine_for(p, a.K, a.groups) : SDN_SPREAD_GATHER;
-  if (engine != SDN_SPREAD_GATHER) {
-    // value scale: the largest component of the residuals (unless the
-    // interpolation that produced them recorded it) and of V
-    if (a.src_max_ready) {
-      hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, p.absmax + 1, 1);
-    } else {
-      hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, p.absmax, 2);
-      const size_t nsrc = (size_t)a.groups * p.M;
-      const unsigned nblk = (unsigned)std::min<size_t>(2048, (nsrc + 1023) / 1024);
-      hipLaunchKernelGGL(k_absmax, dim3(nblk), dim3(256), 0, st, a.src, nsrc, p.absmax);
-    }
-    hipLaunchKernelGGL(k_absmax, dim3(1), dim3(256), 0, st, a.V, (size_t)p.T * a.K,
-                       p.absmax + 1);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    if (engine == SDN_SPREAD_PLANES) {
-      switch (p.W) {
-        case 4: e = spread_pw<4>(d, a.K, grd, p.absmax, st); break;
-        case 8: e = spread_pw<8>(d, a.K, grd, p.absmax, st); break;
-        default: e = spread_pw<6>(d, a.K, grd, p.absmax, st); break;
-      }
-    } else {
-      switch (p.W) {
-        case 4: e = spread_mma<4, true>(d, a.K, grd, p.absmax, st); break;
-        case 8: e = spread_mma<8, true>(d, a.K, grd, p.absmax, st); break;
-        default: e = spread_mma<6, true>(d, a.K, grd, p.absmax, st); break;
-      }
-    }
+  d.absmax = p.absmax;
+  return d;
+}
+
+bool spread_args_ok(const sdn_plan_s &p, const SpreadArgs &a) {
+  if (p.M == 0 || p.sitems == nullptr) return false;
+  if (a.src_plan_order && a.V == nullptr) return false;
+  if (p.nslots > 0 && a.part == nullptr) return false;
+  return a.K >= 1 && a.K <= kMaxK;
+}
+
+// The matrix engines' value scale: the largest component of the values
+// (unless the interpolation that produced them recorded it) and of V.
+hipError_t spread_scale(const sdn_plan_s &p, const SpreadArgs &a, hipStream_t st) {
+  if (a.src_max_ready) {
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, p.absmax + 1, 1);
   } else {
-    switch (p.W) {
-      case 4: e = mix ? spread_k<4, true>(d, a.K, grd, st) : spread_k<4, false>(d, a.K, grd, st); break;
-      case 8: e = mix ? spread_k<8, true>(d, a.K, grd, st) : spread_k<8, false>(d, a.K, grd, st); break;
-      default: e = mix ? spread_k<6, true>(d, a.K, grd, st) : spread_k<6, false>(d, a.K, grd, st); break;
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, p.absmax, 2);
+    const size_t nsrc = (size_t)a.groups * p.M;
+    const unsigned nblk = (unsigned)std::min<size_t>(2048, (nsrc + 1023) / 1024);
+    hipLaunchKernelGGL(k_absmax, dim3(nblk), dim3(256), 0, st, a.src, nsrc, p.absmax);
+  }
+  hipLaunchKernelGGL(k_absmax, dim3(1), dim3(256), 0, st, a.V, (size_t)p.T * a.K, p.absmax + 1);
+  return hipGetLastError();
+}
+
+hipError_t spread_engine_launch(const SpreadDev &d, const Fused<SpreadDev> *fz, int engine, int W,
+                                bool mix, int K, dim3 grd, hipStream_t st) {
+  if (engine == SDN_SPREAD_PLANES) {
+    switch (W) {
+      case 4: return spread_pw<4>(d, fz, K, grd, st);
+      case 8: return spread_pw<8>(d, fz, K, grd, st);
+      default: return spread_pw<6>(d, fz, K, grd, st);
     }
   }
-  if (e != hipSuccess || p.nsplit == 0) return e;
-  hipLaunchKernelGGL(k_spread_reduce, dim3((unsigned)p.nsplit, (unsigned)a.groups), dim3(kThreads),
-                     0, st, d, (const int4 *)p.splits, a.K);
+  if (engine == SDN_SPREAD_MATRIX) {
+    switch (W) {
+      case 4: return spread_mma<4, true>(d, fz, K, grd, st);
+      case 8: return spread_mma<8, true>(d, fz, K, grd, st);
+      default: return spread_mma<6, true>(d, fz, K, grd, st);
+    }
+  }
+  switch (W) {
+    case 4: return mix ? spread_k<4, true>(d, fz, K, grd, st) : spread_k<4, false>(d, fz, K, grd, st);
+    case 8: return mix ? spread_k<8, true>(d, fz, K, grd, st) : spread_k<8, false>(d, fz, K, grd, st);
+    default: return mix ? spread_k<6, true>(d, fz, K, grd, st) : spread_k<6, false>(d, fz, K, grd, st);
+  }
+}
+
+// Sum of the partial blocks of the plan's crowded blocks.
+hipError_t spread_reduce(const sdn_plan_s &p, const SpreadDev &d, int K, hipStream_t st) {
+  if (p.nsplit == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_spread_reduce, dim3((unsigned)p.nsplit, (unsigned)d.groups), dim3(kThreads),
+                     0, st, d, (const int4 *)p.splits, K);
   return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_spread(const sdn_plan_s &p, const SpreadArgs &a, hipStream_t st) {
+  if (!spread_args_ok(p, a)) return hipErrorInvalidValue;
+  const SpreadDev d = spread_dev(p, a);
+  const bool mix = a.V != nullptr;
+  const int engine = mix ? spread_engine_for(p, a.K, a.groups) : SDN_SPREAD_GATHER;
+  hipError_t e = engine != SDN_SPREAD_GATHER ? spread_scale(p, a, st) : hipSuccess;
+  if (e != hipSuccess) return e;
+  e = spread_engine_launch(d, nullptr, engine, p.W, mix, a.K,
+                           dim3((unsigned)p.nsitems, (unsigned)a.groups), st);
+  if (e != hipSuccess) return e;
+  return spread_reduce(p, d, a.K, st);
+}
+
+hipError_t launch_spread_fused(const sdn_plan_s *const *plans, const SpreadArgs *args, int n,
+                               hipStream_t st) {
+  if (n < 1 || n > kMaxFused) return hipErrorInvalidValue;
+  const bool mix = args[0].V != nullptr;
+  const int K = args[0].K, groups = args[0].groups, W = plans[0]->W;
+  const int engine = mix ? spread_engine_for(*plans[0], K, groups) : SDN_SPREAD_GATHER;
+  Fused<SpreadDev> f{};
+  f.n = n;
+  int total = 0;
+  for (int v = 0; v < n; ++v) {
+    const sdn_plan_s &p = *plans[v];
+    const SpreadArgs &a = args[v];
+    if (!spread_args_ok(p, a) || p.W != W || a.K != K || a.groups != groups ||
+        (a.V != nullptr) != mix || (mix ? spread_engine_for(p, K, groups) : SDN_SPREAD_GATHER) != engine)
+      return hipErrorInvalidValue;
+    f.dev[v] = spread_dev(p, a);
+    f.start[v] = total;
+    total += (int)p.nsitems;
+    if (engine != SDN_SPREAD_GATHER) {
+      const hipError_t e = spread_scale(p, a, st);
+      if (e != hipSuccess) return e;
+    }
+  }
+  f.start[n] = total;
+  hipError_t e = spread_engine_launch(f.dev[0], &f, engine, W, mix, K,
+                                      dim3((unsigned)total, (unsigned)groups), st);
+  for (int v = 0; v < n && e == hipSuccess; ++v) e = spread_reduce(*plans[v], f.dev[v], K, st);
+  return e;
 }
 
 hipError_t launch_fill_zero(float2 *a, size_t n, hipStream_t st) {

@@ -1,6 +1,11 @@
 // Ragged volumes: several plans (image shapes, trajectories) evaluated as
-// one call.  Each stage runs per volume on the caller's stream, in volume
-// order; the group adds only the loss reduction over volumes.
+// one call on the caller's stream.  The interpolation and the spreading of
+// all volumes each run as one launch over the work items of every volume
+// (the FFT passes, whose lengths differ between volumes, run volume by
+// volume); volumes that cannot share those launches (different kernel
+// widths or spreading engines, coil passes under a workspace budget, more
+// than eight volumes) run each member plan's call in turn.  The group adds
+// the loss reduction over volumes.
 #include <vector>
 
 #include "sdn_internal.h"
@@ -73,6 +78,9 @@ sdn_status sdn_group_mrf_forward(sdn_group g, const void *const *x, int K,
   SDN_GROUP_CHECK(g, "sdn_group_mrf_forward");
   if (!x || !smaps || !C || !coil_idx || !V || !y)
     return fail(SDN_E_INVALID, "sdn_group_mrf_forward: null argument array");
+  const sdn_status fs = group_forward_fused(g->plans.data(), (int)g->plans.size(), x, K, smaps, C,
+                                            coil_idx, B, V, y, stream);
+  if (fs != SDN_E_UNSUPPORTED) return fs;
   for (size_t v = 0; v < g->plans.size(); ++v) {
     const sdn_status s = sdn_mrf_forward(g->plans[v], x[v], K, smaps[v], C[v], coil_idx[v], B,
                                          V[v], y[v], stream);
@@ -88,6 +96,9 @@ sdn_status sdn_group_mrf_adjoint(sdn_group g, const void *const *y, int K,
   SDN_GROUP_CHECK(g, "sdn_group_mrf_adjoint");
   if (!y || !smaps || !C || !coil_idx || !V || !x_out)
     return fail(SDN_E_INVALID, "sdn_group_mrf_adjoint: null argument array");
+  const sdn_status fs = group_adjoint_fused(g->plans.data(), (int)g->plans.size(), y, K, smaps, C,
+                                            coil_idx, B, V, x_out, accumulate, stream);
+  if (fs != SDN_E_UNSUPPORTED) return fs;
   for (size_t v = 0; v < g->plans.size(); ++v) {
     const sdn_status s = sdn_mrf_adjoint(g->plans[v], y[v], K, smaps[v], C[v], coil_idx[v], B,
                                          V[v], x_out[v], accumulate, stream);
@@ -105,7 +116,10 @@ sdn_status sdn_group_mrf_dc_grad(sdn_group g, const void *const *x, int K,
   if (!x || !smaps || !C || !coil_idx || !V || !d || !grad || !loss)
     return fail(SDN_E_INVALID, "sdn_group_mrf_dc_grad: null argument");
   const int n = (int)g->plans.size();
-  for (int v = 0; v < n; ++v) {
+  const sdn_status fs = group_dc_grad_fused(g->plans.data(), n, x, K, smaps, C, coil_idx, B, V, d,
+                                            w, g->losses, grad, stream);
+  if (fs != SDN_E_UNSUPPORTED && fs != SDN_OK) return fs;
+  for (int v = 0; v < n && fs == SDN_E_UNSUPPORTED; ++v) {
     const sdn_status s = sdn_mrf_dc_grad(g->plans[v], x[v], K, smaps[v], C[v], coil_idx[v], B,
                                          V[v], d[v], w ? w[v] : nullptr, g->losses + v,
                                          grad[v], stream);

@@ -247,6 +247,31 @@ struct SpreadArgs {
                       // of src (written by the interpolation that produced it)
 };
 hipError_t launch_spread(const sdn_plan_s &p, const SpreadArgs &a, hipStream_t st);
+// Ragged volumes: the interpolation / spreading of up to kMaxFusedPlans
+// plans (same kernel width, coils and channels; for spreading the same
+// engine) as one launch over all their work items.
+constexpr int kMaxFusedPlans = 8;
+hipError_t launch_interp_fused(const sdn_plan_s *const *plans, const InterpArgs *args, int n,
+                               hipStream_t st);
+hipError_t launch_spread_fused(const sdn_plan_s *const *plans, const SpreadArgs *args, int n,
+                               hipStream_t st);
+
+// Ragged-volume group calls with one interpolation and one spreading launch
+// for all volumes (api.hip); SDN_E_UNSUPPORTED, with nothing enqueued, when
+// the volumes cannot share those launches.
+sdn_status group_dc_grad_fused(sdn_plan const *plans, int n, const void *const *x, int K,
+                               const void *const *smaps, const int *C,
+                               const int32_t *const *coil_idx, int B, const void *const *V,
+                               const void *const *d, const float *const *w, double *losses,
+                               void *const *grad, void *stream);
+sdn_status group_forward_fused(sdn_plan const *plans, int n, const void *const *x, int K,
+                               const void *const *smaps, const int *C,
+                               const int32_t *const *coil_idx, int B, const void *const *V,
+                               void *const *y, void *stream);
+sdn_status group_adjoint_fused(sdn_plan const *plans, int n, const void *const *y, int K,
+                               const void *const *smaps, const int *C,
+                               const int32_t *const *coil_idx, int B, const void *const *V,
+                               void *const *x_out, int accumulate, void *stream);
 // Engine (SDN_SPREAD_GATHER, _MATRIX or _PLANES) of a subspace-mixing
 // spreading call with K channels per group and `groups` groups (coils).
 int spread_engine_for(const sdn_plan_s &p, int K, int groups);

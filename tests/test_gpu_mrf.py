@@ -226,3 +226,4 @@ def test_adjoint_coil_counts_of_the_fused_inverse_x_pass(B):
     ref = omrf.adjoint(omrf.Nufft(shape, "gridding"), r, smaps, ci, V, frame,
                        traj.astype(np.float64), K)
     assert rel(ab, ref) < 2e-5
+

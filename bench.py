@@ -317,6 +317,7 @@ def measure(workload, a, steps, warmup, dev, torch, sdn, wl, headline):
         "config": config,
     }
     if a.only_step:
+        _calibration_copy(a, dev, torch)
         return {"out": out, "vols": vols}
 
     # per-stage breakdown: eager steps with HIP events around every launch,
@@ -396,13 +397,7 @@ def measure(workload, a, steps, warmup, dev, torch, sdn, wl, headline):
             if v["pplan"] is not v["plan"]:
                 v["pplan"].close()
             v["pplan"] = None
-    if a.calib_copy_mb > 0:
-        n = a.calib_copy_mb * (1 << 20) // 4
-        src = torch.ones(n, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+    _calibration_copy(a, dev, torch)
 
     # algorithmic bytes and flops of one step per stage, summed over volumes;
     # a single volume's step launches each stage once (or once per coil chunk,
@@ -446,6 +441,19 @@ def measure(workload, a, steps, warmup, dev, torch, sdn, wl, headline):
     if group is not None:
         group.close()
     return {"out": out, "vols": vols}
+
+
+def _calibration_copy(a, dev, torch):
+    """One fill and one device copy of --calib-copy-mb MiB: known traffic for
+    scaling the HBM counters."""
+    if a.calib_copy_mb <= 0:
+        return
+    n = a.calib_copy_mb * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
 
 
 def roofline(stages, sb, sf, steps, vols, B, K, engine, workload):

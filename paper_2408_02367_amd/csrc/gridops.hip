@@ -65,11 +65,34 @@ struct Fused {
   Dev dev[kMaxFused];
 };
 
+// Work order over the 8 XCDs.  The hardware deals the workgroups of a
+// launch out to the XCDs round-robin (workgroup L to XCD L % 8), and each
+// XCD has its own L2.  The groups (coils or coil groups) of one work item
+// read the same point records, so they go to one XCD one after another:
+// XCD j runs items j, j + 8, j + 16, ... (the plan's item order, heaviest
+// first, is kept across the XCDs), each for all groups in turn.  The grid
+// holds xcd_grid(items, groups) workgroups; those past the last item exit.
+constexpr int kXcds = 8;
+inline unsigned xcd_grid(int64_t items, int groups) {
+  return (unsigned)((items + kXcds - 1) / kXcds * kXcds * groups);
+}
+__device__ __forceinline__ bool xcd_item(int items, int groups, int &item, int &group) {
+  const int j = (int)blockIdx.x % kXcds, r = (int)blockIdx.x / kXcds;
+  const int q = r / groups;
+  item = q * kXcds + j;
+  group = r - q * groups;
+  return item < items;
+}
+
+// Volume, item and group of this workgroup of a fused launch (items counted
+// over all volumes: start[] are item offsets); -1 past the last item.
 template <typename Dev>
-__device__ __forceinline__ int fused_volume(const Fused<Dev> &f, int &item) {
+__device__ __forceinline__ int fused_volume(const Fused<Dev> &f, int groups, int &item,
+                                            int &group) {
+  if (!xcd_item(f.start[f.n], groups, item, group)) return -1;
   int v = 0;
-  while (v + 1 < f.n && (int)blockIdx.x >= f.start[v + 1]) ++v;
-  item = (int)blockIdx.x - f.start[v];
+  while (v + 1 < f.n && item >= f.start[v + 1]) ++v;
+  item -= f.start[v];
   return v;
 }
 
@@ -94,6 +117,7 @@ struct InterpDev {
   float rscale;
   unsigned *rmax;
   int nitems;          // work items of this plan (the loss partials' row length)
+  int groups;          // output rows per point: coils (mix) or channel groups
 };
 
 constexpr int kThreads = 256;
@@ -131,7 +155,7 @@ __device__ __forceinline__ void interp_epilogue(const InterpDev &a, const int4 &
       const float sw = a.rscale * wt;
       const float2 rv = make_float2(sw * df.x, sw * df.y);
       my_max = fmaxf(my_max, fmaxf(fabsf(rv.x), fabsf(rv.y)));
-      a.r_plan[(size_t)(wi.y + q) * gridDim.y + grp] = rv;
+      a.r_plan[(size_t)(wi.y + q) * a.groups + grp] = rv;
     } else {
       a.y[(size_t)grp * a.M + orig] = acc[i];
     }
@@ -158,20 +182,19 @@ __device__ __forceinline__ void interp_epilogue(const InterpDev &a, const int4 &
       if (a.rmax) atomicMax(a.rmax, __float_as_uint(mx));
       // the partials are summed afterwards in a fixed order, so the loss
       // does not depend on the order in which workgroups finish
-      a.loss_part[(size_t)blockIdx.y * a.nitems + item] = s;
+      a.loss_part[(size_t)grp * a.nitems + item] = s;
     }
   }
 }
 
 template <int W, bool MIX, bool DC, bool BUF>
-__device__ __forceinline__ void interp_body(const InterpDev &a, int item) {
+__device__ __forceinline__ void interp_body(const InterpDev &a, int item, int grp) {
   extern __shared__ float2 tile[];
   // raw buffer over the transposed records (word 3: the gfx9 raw-buffer format)
   const __amdgpu_buffer_rsrc_t wrsrc = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<float *>(a.wts_t), 0, (int)a.rec_bytes, 0x00020000);
   const TileGeom &g = a.g;
   const int4 wi = a.work[item];
-  const int grp = blockIdx.y;
   const int tid = threadIdx.x;
   const int tz = wi.x / (g.ntx * g.nty);
   const int rem = wi.x - tz * (g.ntx * g.nty);
@@ -288,16 +311,20 @@ __device__ __forceinline__ void interp_body(const InterpDev &a, int item) {
   if constexpr (MIX) interp_epilogue<DC>(a, wi, grp, tid, acc, item);
 }
 
+// grid: items x groups workgroups (one dimension), in XCD order
 template <int W, bool MIX, bool DC, bool BUF>
 __global__ void __launch_bounds__(kIThreads) k_interp(InterpDev a) {
-  interp_body<W, MIX, DC, BUF>(a, (int)blockIdx.x);
+  int item, grp;
+  if (!xcd_item(a.nitems, a.groups, item, grp)) return;
+  interp_body<W, MIX, DC, BUF>(a, item, grp);
 }
 
 template <int W, bool MIX, bool DC, bool BUF>
 __global__ void __launch_bounds__(kIThreads) k_interp_fused(Fused<InterpDev> f) {
-  int item;
-  const int v = fused_volume(f, item);
-  interp_body<W, MIX, DC, BUF>(f.dev[v], item);
+  int item, grp;
+  const int v = fused_volume(f, f.dev[0].groups, item, grp);
+  if (v < 0) return;
+  interp_body<W, MIX, DC, BUF>(f.dev[v], item, grp);
 }
 
 struct SpreadDev {
@@ -318,6 +345,8 @@ struct SpreadDev {
   const float2 *src;   // mix: [groups][M]; else [groups * K][M]
   int src_plan;
   const unsigned *absmax;  // matrix engines: largest input magnitudes (value scale)
+  int nitems;          // spreading items of this plan
+  int cgroups;         // coil groups (workgroups per item) of the launch
 };
 
 constexpr int kSB = kSpreadBlock;           // 8
@@ -388,14 +417,13 @@ __device__ __forceinline__ void pull_run(const float *bf, int v0, int v1, int l0
 }
 
 template <int W, bool MIX, int K>
-__device__ __forceinline__ void spread_gather_body(const SpreadDev &a, int item) {
+__device__ __forceinline__ void spread_gather_body(const SpreadDev &a, int item, int grp) {
   static_assert(W <= 8 && kSB == 8 && kVisitOffsets == 16, "offset cases cover -7 .. 7");
   using R = PullRec<W, K>;
   constexpr int RS = R::stride;
   __shared__ float4 batch[64 * RS / 4];
   float *bf = reinterpret_cast<float *>(batch);
   const int4 it = a.items[item];
-  const int grp = blockIdx.y;
   const int lane = threadIdx.x;
   const int bzi = it.x / (a.nbx * a.nby);
   const int rem = it.x - bzi * (a.nbx * a.nby);
@@ -492,16 +520,21 @@ __device__ __forceinline__ void spread_gather_body(const SpreadDev &a, int item)
   }
 }
 
+// grids of the spreading kernels: items x coil groups workgroups (one
+// dimension, XCD order); a.cgroups coil groups of the launch
 template <int W, bool MIX, int K>
 __global__ void __launch_bounds__(64) k_spread(SpreadDev a) {
-  spread_gather_body<W, MIX, K>(a, (int)blockIdx.x);
+  int item, grp;
+  if (!xcd_item(a.nitems, a.cgroups, item, grp)) return;
+  spread_gather_body<W, MIX, K>(a, item, grp);
 }
 
 template <int W, bool MIX, int K>
 __global__ void __launch_bounds__(64) k_spread_fused(Fused<SpreadDev> f) {
-  int item;
-  const int v = fused_volume(f, item);
-  spread_gather_body<W, MIX, K>(f.dev[v], item);
+  int item, grp;
+  const int v = fused_volume(f, f.dev[0].cgroups, item, grp);
+  if (v < 0) return;
+  spread_gather_body<W, MIX, K>(f.dev[v], item, grp);
 }
 
 // ---------------------------------------------------------------------------
@@ -639,7 +672,7 @@ __device__ __forceinline__ void mma_fetch(const SpreadDev &a, const MmaList &L, 
 }
 
 template <int W, bool MIX, int K, int NG>
-__device__ __forceinline__ void spread_mma_body(const SpreadDev &a, int item) {
+__device__ __forceinline__ void spread_mma_body(const SpreadDev &a, int item, int cg) {
   const unsigned *absmax = a.absmax;
   // values per entry and coil: [re/im][k], K padded to even so that a lane
   // reads its component's K values with 8-byte loads
@@ -654,11 +687,11 @@ __device__ __forceinline__ void spread_mma_body(const SpreadDev &a, int item) {
   __shared__ uint4 sA[2][2][4][64];   // [buffer][hi/lo][row tile][lane]: (y,x) operand fragments
   const int4 it = a.items[item];
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
-  const int grp = blockIdx.y * NG + wv;
+  const int grp = cg * NG + wv;
   const bool coil_ok = grp < a.groups;
   const bool v_wave = MIX && wv == NG - 1;   // loads the basis values for all coils
   const bool r_wave = MIX && wv == (NG > 1 ? 1 : 0);   // loads the residuals of all coils
-  const int g0 = blockIdx.y * NG;
+  const int g0 = cg * NG;
   const int bzi = it.x / (a.nbx * a.nby);
   const int rem = it.x - bzi * (a.nbx * a.nby);
   const int byi = rem / a.nbx, bxi = rem - byi * a.nbx;
@@ -852,14 +885,17 @@ __device__ __forceinline__ void spread_mma_body(const SpreadDev &a, int item) {
 
 template <int W, bool MIX, int K, int NG>
 __global__ void __launch_bounds__(64 * NG) k_spread_mma(SpreadDev a) {
-  spread_mma_body<W, MIX, K, NG>(a, (int)blockIdx.x);
+  int item, cg;
+  if (!xcd_item(a.nitems, a.cgroups, item, cg)) return;
+  spread_mma_body<W, MIX, K, NG>(a, item, cg);
 }
 
 template <int W, bool MIX, int K, int NG>
 __global__ void __launch_bounds__(64 * NG) k_spread_mma_fused(Fused<SpreadDev> f) {
-  int item;
-  const int v = fused_volume(f, item);
-  spread_mma_body<W, MIX, K, NG>(f.dev[v], item);
+  int item, cg;
+  const int v = fused_volume(f, f.dev[0].cgroups, item, cg);
+  if (v < 0) return;
+  spread_mma_body<W, MIX, K, NG>(f.dev[v], item, cg);
 }
 
 // ---------------------------------------------------------------------------
@@ -913,7 +949,7 @@ struct PwList {
 };
 
 template <int W, int K, int NCT>
-__device__ __forceinline__ void spread_pw_body(const SpreadDev &a, int item) {
+__device__ __forceinline__ void spread_pw_body(const SpreadDev &a, int item, int cg) {
   const unsigned *absmax = a.absmax;
   constexpr int GMAX = pw_coils(W, K);        // coils of a full workgroup
   constexpr int NVP = (K + 1) / 2;            // basis pieces per entry
@@ -931,7 +967,7 @@ __device__ __forceinline__ void spread_pw_body(const SpreadDev &a, int item) {
 
   const int4 it = a.items[item];
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
-  const int g0 = blockIdx.y * GMAX;
+  const int g0 = cg * GMAX;
   const int G = min(GMAX, a.groups - g0);     // coils of this workgroup
   const int bzi = it.x / (a.nbx * a.nby);
   const int rem = it.x - bzi * (a.nbx * a.nby);
@@ -1179,14 +1215,17 @@ __device__ __forceinline__ void spread_pw_body(const SpreadDev &a, int item) {
 
 template <int W, int K, int NCT>
 __global__ void __launch_bounds__(64 * kPwWaves) k_spread_pw(SpreadDev a) {
-  spread_pw_body<W, K, NCT>(a, (int)blockIdx.x);
+  int item, cg;
+  if (!xcd_item(a.nitems, a.cgroups, item, cg)) return;
+  spread_pw_body<W, K, NCT>(a, item, cg);
 }
 
 template <int W, int K, int NCT>
 __global__ void __launch_bounds__(64 * kPwWaves) k_spread_pw_fused(Fused<SpreadDev> f) {
-  int item;
-  const int v = fused_volume(f, item);
-  spread_pw_body<W, K, NCT>(f.dev[v], item);
+  int item, cg;
+  const int v = fused_volume(f, f.dev[0].cgroups, item, cg);
+  if (v < 0) return;
+  spread_pw_body<W, K, NCT>(f.dev[v], item, cg);
 }
 
 // Largest |component| of n complex values, as float bits (non-negative
@@ -1376,6 +1415,7 @@ InterpDev interp_dev(const sdn_plan_s &p, const InterpArgs &a) {
   d.rscale = a.rscale;
   d.rmax = a.dc ? a.rmax : nullptr;
   d.nitems = (int)p.nwork;
+  d.groups = a.groups;
   return d;
 }
 
@@ -1402,7 +1442,7 @@ hipError_t launch_interp(const sdn_plan_s &p, const InterpArgs &a, hipStream_t s
   const bool dc = a.dc != 0;
   const size_t lds = interp_lds_bytes(p);
   if (d.rmax) hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, d.rmax, 1);
-  dim3 grd((unsigned)p.nwork, (unsigned)a.groups);
+  dim3 grd(xcd_grid(p.nwork, a.groups));
   hipError_t e;
   switch (p.W) {
     case 4: e = interp_launch<4>(d, nullptr, d.rec_bytes != 0, mix, dc, grd, lds, st); break;
@@ -1436,7 +1476,7 @@ hipError_t launch_interp_fused(const sdn_plan_s *const *plans, const InterpArgs 
     if (f.dev[v].rmax) hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, f.dev[v].rmax, 1);
   }
   f.start[n] = total;
-  dim3 grd((unsigned)total, (unsigned)args[0].groups);
+  dim3 grd(xcd_grid(total, args[0].groups));
   hipError_t e;
   switch (plans[0]->W) {
     case 4: e = interp_launch<4>(f.dev[0], &f, buf, mix, dc, grd, lds, st); break;
@@ -1455,12 +1495,20 @@ size_t spread_part_elems(const sdn_plan_s &p, int groups, int K) {
 }
 
 namespace {
+// The launch grids: items x coil groups workgroups; the coil-group count
+// goes into the descriptors.
+unsigned spread_grid(SpreadDev &d, Fused<SpreadDev> *fz, int cgroups) {
+  d.cgroups = cgroups;
+  if (!fz) return xcd_grid(d.nitems, cgroups);
+  for (int v = 0; v < fz->n; ++v) fz->dev[v].cgroups = cgroups;
+  return xcd_grid(fz->start[fz->n], cgroups);
+}
+
 template <int W, bool MIX>
-hipError_t spread_mma(const SpreadDev &d, const Fused<SpreadDev> *fz, int K, dim3 grd,
-                      hipStream_t st) {
+hipError_t spread_mma(SpreadDev d, Fused<SpreadDev> *fz, int K, hipStream_t st) {
   // up to four coils per workgroup, one wave each
   const int ng = std::min(d.groups, 4);
-  grd.y = (unsigned)((d.groups + ng - 1) / ng);
+  const dim3 grd(spread_grid(d, fz, (d.groups + ng - 1) / ng));
   switch (K * 8 + ng) {
 #define SDN_SPM(KV, NGV)                                                                    \
   case KV * 8 + NGV:                                                                        \
@@ -1479,15 +1527,14 @@ hipError_t spread_mma(const SpreadDev &d, const Fused<SpreadDev> *fz, int K, dim
 }
 
 template <int W>
-hipError_t spread_pw(const SpreadDev &d, const Fused<SpreadDev> *fz, int K, dim3 grd,
-                     hipStream_t st) {
+hipError_t spread_pw(SpreadDev d, Fused<SpreadDev> *fz, int K, hipStream_t st) {
   // a workgroup takes up to pw_coils(K) coils: 2 K value columns each, in
   // 16-column tiles (5 tiles run as 6)
   const int gmax = pw_coils(W, K);
   const int G = std::min(d.groups, gmax);
   int nct = (2 * K * G + 15) / 16;
   if (nct == 5) nct = 6;
-  grd.y = (unsigned)((d.groups + gmax - 1) / gmax);
+  const dim3 grd(spread_grid(d, fz, (d.groups + gmax - 1) / gmax));
   switch (K * 8 + nct) {
 #define SDN_SPW(KV, NV)                                                                         \
   case KV * 8 + NV:                                                                             \
@@ -1527,8 +1574,8 @@ int spread_engine_for(const sdn_plan_s &p, int K, int groups) {
 namespace {
 
 template <int W, bool MIX>
-hipError_t spread_k(const SpreadDev &d, const Fused<SpreadDev> *fz, int K, dim3 grd,
-                    hipStream_t st) {
+hipError_t spread_k(SpreadDev d, Fused<SpreadDev> *fz, int K, hipStream_t st) {
+  const dim3 grd(spread_grid(d, fz, d.groups));
   switch (K) {
 #define SDN_SPK(KV)                                                                     \
   case KV:                                                                              \
@@ -1564,6 +1611,8 @@ SpreadDev spread_dev(const sdn_plan_s &p, const SpreadArgs &a) {
   d.src = a.src;
   d.src_plan = a.src_plan_order ? 1 : 0;
   d.absmax = p.absmax;
+  d.nitems = (int)p.nsitems;
+  d.cgroups = a.groups;
   return d;
 }
 
@@ -1589,26 +1638,26 @@ hipError_t spread_scale(const sdn_plan_s &p, const SpreadArgs &a, hipStream_t st
   return hipGetLastError();
 }
 
-hipError_t spread_engine_launch(const SpreadDev &d, const Fused<SpreadDev> *fz, int engine, int W,
-                                bool mix, int K, dim3 grd, hipStream_t st) {
+hipError_t spread_engine_launch(const SpreadDev &d, Fused<SpreadDev> *fz, int engine, int W,
+                                bool mix, int K, hipStream_t st) {
   if (engine == SDN_SPREAD_PLANES) {
     switch (W) {
-      case 4: return spread_pw<4>(d, fz, K, grd, st);
-      case 8: return spread_pw<8>(d, fz, K, grd, st);
-      default: return spread_pw<6>(d, fz, K, grd, st);
+      case 4: return spread_pw<4>(d, fz, K, st);
+      case 8: return spread_pw<8>(d, fz, K, st);
+      default: return spread_pw<6>(d, fz, K, st);
     }
   }
   if (engine == SDN_SPREAD_MATRIX) {
     switch (W) {
-      case 4: return spread_mma<4, true>(d, fz, K, grd, st);
-      case 8: return spread_mma<8, true>(d, fz, K, grd, st);
-      default: return spread_mma<6, true>(d, fz, K, grd, st);
+      case 4: return spread_mma<4, true>(d, fz, K, st);
+      case 8: return spread_mma<8, true>(d, fz, K, st);
+      default: return spread_mma<6, true>(d, fz, K, st);
     }
   }
   switch (W) {
-    case 4: return mix ? spread_k<4, true>(d, fz, K, grd, st) : spread_k<4, false>(d, fz, K, grd, st);
-    case 8: return mix ? spread_k<8, true>(d, fz, K, grd, st) : spread_k<8, false>(d, fz, K, grd, st);
-    default: return mix ? spread_k<6, true>(d, fz, K, grd, st) : spread_k<6, false>(d, fz, K, grd, st);
+    case 4: return mix ? spread_k<4, true>(d, fz, K, st) : spread_k<4, false>(d, fz, K, st);
+    case 8: return mix ? spread_k<8, true>(d, fz, K, st) : spread_k<8, false>(d, fz, K, st);
+    default: return mix ? spread_k<6, true>(d, fz, K, st) : spread_k<6, false>(d, fz, K, st);
   }
 }
 
@@ -1629,8 +1678,7 @@ hipError_t launch_spread(const sdn_plan_s &p, const SpreadArgs &a, hipStream_t s
   const int engine = mix ? spread_engine_for(p, a.K, a.groups) : SDN_SPREAD_GATHER;
   hipError_t e = engine != SDN_SPREAD_GATHER ? spread_scale(p, a, st) : hipSuccess;
   if (e != hipSuccess) return e;
-  e = spread_engine_launch(d, nullptr, engine, p.W, mix, a.K,
-                           dim3((unsigned)p.nsitems, (unsigned)a.groups), st);
+  e = spread_engine_launch(d, nullptr, engine, p.W, mix, a.K, st);
   if (e != hipSuccess) return e;
   return spread_reduce(p, d, a.K, st);
 }
@@ -1659,8 +1707,7 @@ hipError_t launch_spread_fused(const sdn_plan_s *const *plans, const SpreadArgs 
     }
   }
   f.start[n] = total;
-  hipError_t e = spread_engine_launch(f.dev[0], &f, engine, W, mix, K,
-                                      dim3((unsigned)total, (unsigned)groups), st);
+  hipError_t e = spread_engine_launch(f.dev[0], &f, engine, W, mix, K, st);
   for (int v = 0; v < n && e == hipSuccess; ++v) e = spread_reduce(*plans[v], f.dev[v], K, st);
   return e;
 }

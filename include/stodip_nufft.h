@@ -224,10 +224,15 @@ SDN_API sdn_status sdn_mrf_dc_grad_noalloc(sdn_plan plan, const void *x, int K, 
 
 /*
  * Ragged volumes: a group of plans of different image shapes, each with its
- * own trajectory (and V), evaluated as one call on one stream (the batched
- * form over several volumes; Sec. 3 reconstructs many scans with one
- * operator).  Every stage is launched per volume, in volume order; results
- * equal those of the member plans called one by one.
+ * own trajectory (and V), evaluated as one call on one stream (Sec. 3.1
+ * evaluates five scanned volumes; each is reconstructed on its own, and the
+ * group only shares launches between them).  The interpolation and the
+ * spreading each run as one launch over the work items of all volumes; the
+ * FFT passes run volume by volume.  Volumes that cannot share those
+ * launches (different kernel widths or spreading engines, coil passes under
+ * a workspace budget, more than eight volumes) run the member plans' calls
+ * in turn.  Either way the results equal those of the member plans called
+ * one by one, bit for bit.
  *
  *   sdn_group_create  plans: host array of n >= 1 live plans (not owned: they
  *                     must outlive the group); the group holds n doubles of

@@ -4,7 +4,7 @@ vector-ALU gather spreading with the subspace mix (GPU).
 A call with a single coil spreads through the gather engine with the mix
 fused in (one wave per spreading block, K channels in registers); the
 matrix-core engine serves calls of several coils unless the plan forces the
-gather.  These tests run that engine at K = 5 and 6 (one coil, as the
+gather.  These tests run that engine at K = 5, 6 and 8 (one coil, as the
 paper's step and the paper-shaped benchmark row do) and forced at several
 coils, against the FP64 oracle: the direct NUDFT (<= 1e-4 relative l2) and
 the FP64 gridding NUFFT with the same kernel (<= 5e-6).
@@ -59,9 +59,9 @@ def _check_grad_and_adjoint(c, p):
         assert rel(xb[k], ref_g[k]) < 5e-6
 
 
-@pytest.mark.parametrize("K", [5, 6])
+@pytest.mark.parametrize("K", [5, 6, 8])
 def test_one_coil_gradient_and_adjoint(K):
-    c = _case(K, 1)
+    c = _case(K, 1, T=max(7, K + 2))
     _check_grad_and_adjoint(c, _plan(c))
 
 

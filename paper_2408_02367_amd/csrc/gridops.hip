@@ -926,18 +926,20 @@ __global__ void __launch_bounds__(64 * NG) k_spread_mma_fused(Fused<SpreadDev> f
 // cells, so that no kernel support can touch both ends of a block.
 constexpr int kPwWaves = 16;                  // waves of a plane-split workgroup
 constexpr int kPwCols = 96;                   // value columns per workgroup at most
-// Weight rows of the plane-split kernel are 26 floats apart: the four lane
-// groups of a fragment read rows of entries 8 apart, which then start 16
-// banks apart instead of on the same banks.
-constexpr int kPwRow = 26;
+// A staged weight row holds the 8 weights of one axis at the block's own
+// coordinates (zero where the support does not reach); rows are 9 floats
+// apart, so the four lane groups of a fragment, which read rows of entries
+// 8 apart, start 8 banks apart instead of on the same banks.
+constexpr int kPwRow = 9;
 
 // Coils of one plane-split workgroup for kernel width W and K channels:
 // 2 K value columns each, at most kPwCols, and few enough that one fetch
-// set (512 lanes) loads a batch: W record pieces, ceil(K/2) basis pieces
-// and ceil(G/2) residual pieces per entry.
+// set (512 lanes) loads a batch: 3 weight rows, ceil(K/2) basis pieces and
+// ceil(G/2) residual pieces per entry.
 __host__ __device__ constexpr int pw_coils(int W, int K) {
+  static_cast<void>(W);   // the weight rows take three pieces whatever the width
   const int by_cols = kPwCols / (2 * K);
-  const int by_fetch = 2 * (512 / kMmaBatch - W - (K + 1) / 2);
+  const int by_fetch = 2 * (512 / kMmaBatch - 3 - (K + 1) / 2);
   const int g = by_cols < by_fetch ? by_cols : by_fetch;
   return g < 16 ? g : 16;
 }
@@ -954,13 +956,14 @@ __device__ __forceinline__ void spread_pw_body(const SpreadDev &a, int item, int
   constexpr int GMAX = pw_coils(W, K);        // coils of a full workgroup
   constexpr int NVP = (K + 1) / 2;            // basis pieces per entry
   constexpr int NRP = (GMAX + 1) / 2;         // residual pieces per entry
-  static_assert(kMmaBatch * (W + NVP + NRP) <= 512, "one fetch set loads a batch");
+  static_assert(kMmaBatch * (3 + NVP + NRP) <= 512, "one fetch set loads a batch");
+  static_assert(W <= kSB, "a weight row covers the block");
   // double-buffered staging: batch n is staged into buffer n & 1 one
-  // iteration ahead; its value tiles are built into buffer n & 1 and its A
-  // tiles into registers before the barrier of iteration n, and the
-  // products run after it
-  __shared__ float wrow[2][3][kMmaBatch][kPwRow];
-  __shared__ int shifts[2][kMmaBatch];        // x, y, z row shifts; plane mask in bits 24..31
+  // barrier interval ahead; its value tiles are built into buffer n & 1 and
+  // its A tiles into registers in the next interval, and its products run
+  // in the interval after that
+  __shared__ float wsh[2][3][kMmaBatch][kPwRow];  // block-relative weight rows x, y, z
+  __shared__ unsigned pmask[2];                    // planes the entries of a batch touch
   __shared__ float2 vbas[2][kMmaBatch][2 * NVP];
   __shared__ float2 rsd[2][kMmaBatch][2 * NRP];
   __shared__ uint4 sB[2][NCT][2][64];         // [buffer][column tile][hi/lo][lane]
@@ -976,9 +979,6 @@ __device__ __forceinline__ void spread_pw_body(const SpreadDev &a, int item, int
   const float s = value_scale(absmax, true);
   const int nb = (it.z + kMmaBatch - 1) / kMmaBatch;
 
-  // zero the weight rows once; each batch rewrites only the W weights
-  for (int i = tid; i < 2 * 3 * kMmaBatch * kPwRow; i += 64 * kPwWaves) (&wrow[0][0][0][0])[i] = 0.f;
-
   // this wave's row tiles: y pairs 2 h and 2 h + 1 of plane z
   const int z = wv >> 1, h = wv & 1;
   sdn_float4v acc[2][NCT];
@@ -992,22 +992,25 @@ __device__ __forceinline__ void spread_pw_body(const SpreadDev &a, int item, int
   const int fx = r16 & 7, fy = 4 * h + (r16 >> 3);   // A: x, and y of the first tile
 
   // fetch set (wv / 8) loads the batches of its parity; lane q of the set
-  // takes one 16-byte piece of entry pe: a weight-record piece (q < 32 W),
-  // two basis values, or two residuals
+  // takes one piece of entry pe: the W weights of one axis and the packed
+  // first node (q < 96, axis q / 32), two basis values, or two residuals
   const int q = (wv & 7) * 64 + lane;
   const int set = wv >> 3;
   int kind, pe, pc;
-  if (q < kMmaBatch * W) {
-    kind = 0; pe = q / W; pc = q - pe * W;
-  } else if (q < kMmaBatch * (W + NVP)) {
-    kind = 1; pe = (q - kMmaBatch * W) / NVP; pc = q - kMmaBatch * W - pe * NVP;
-  } else if (q < kMmaBatch * (W + NVP + NRP)) {
-    kind = 2; pe = (q - kMmaBatch * (W + NVP)) / NRP; pc = q - kMmaBatch * (W + NVP) - pe * NRP;
+  if (q < 3 * kMmaBatch) {
+    kind = 0; pe = q & (kMmaBatch - 1); pc = q / kMmaBatch;
+  } else if (q < kMmaBatch * (3 + NVP)) {
+    kind = 1; pe = (q - 3 * kMmaBatch) / NVP; pc = q - 3 * kMmaBatch - pe * NVP;
+  } else if (q < kMmaBatch * (3 + NVP + NRP)) {
+    kind = 2; pe = (q - kMmaBatch * (3 + NVP)) / NRP; pc = q - kMmaBatch * (3 + NVP) - pe * NRP;
   } else {
     kind = 3; pe = 0; pc = 0;
   }
+  // the axis of a weight lane: block origin and fine size
+  const int o_ax = pc == 0 ? ox : pc == 1 ? oy : oz;
+  const int nf_ax = pc == 0 ? a.nfx : pc == 1 ? a.nfy : a.nfz;
   PwList L{0, make_int2(0, 0)};
-  float4 fv = make_float4(0.f, 0.f, 0.f, 0.f);
+  float fr[W + 1];                        // this lane's piece of its batch
   // list entry of batch b for this lane's piece
   auto list = [&](int b) {
     const int e = b * kMmaBatch + pe;
@@ -1019,17 +1022,26 @@ __device__ __forceinline__ void spread_pw_body(const SpreadDev &a, int item, int
     L.j = raw < 0 ? ~raw : raw;
     if (kind != 0) L.id = a.vinfo[it.y + e];
   };
-  // this lane's 16-byte piece of batch b (zeros past the list's end)
+  // this lane's piece of batch b (zeros past the list's end)
   auto fetch = [&](int b) {
-    fv = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int i = 0; i <= W; ++i) fr[i] = 0.f;
     if (kind == 3 || b * kMmaBatch + pe >= it.z) return;
     if (kind == 0) {
-      fv = reinterpret_cast<const float4 *>(a.wts + (size_t)L.j * wrec_stride(W))[pc];
+      const float *r = a.wts + (size_t)L.j * wrec_stride(W);
+      const float2 *r2 = reinterpret_cast<const float2 *>(r + pc * W);
+#pragma unroll
+      for (int i = 0; i < W / 2; ++i) {
+        const float2 v = r2[i];
+        fr[2 * i] = v.x;
+        fr[2 * i + 1] = v.y;
+      }
+      fr[W] = r[3 * W];
     } else if (kind == 1) {
       const int k = 2 * pc;
       const float2 v0 = a.V[(size_t)L.id.x * K + k];
       const float2 v1 = k + 1 < K ? a.V[(size_t)L.id.x * K + k + 1] : make_float2(0.f, 0.f);
-      fv = make_float4(v0.x, v0.y, v1.x, v1.y);
+      fr[0] = v0.x; fr[1] = v0.y; fr[2] = v1.x; fr[3] = v1.y;
     } else {
       const int c = 2 * pc;
       float2 r0 = make_float2(0.f, 0.f), r1 = make_float2(0.f, 0.f);
@@ -1041,37 +1053,43 @@ __device__ __forceinline__ void spread_pw_body(const SpreadDev &a, int item, int
         if (c < G) r0 = a.src[(size_t)(g0 + c) * a.M + L.id.y];
         if (c + 1 < G) r1 = a.src[(size_t)(g0 + c + 1) * a.M + L.id.y];
       }
-      fv = make_float4(r0.x, r0.y, r1.x, r1.y);
+      fr[0] = r0.x; fr[1] = r0.y; fr[2] = r1.x; fr[3] = r1.y;
     }
   };
-  // store this lane's piece of batch b into buffer bf
+  // store this lane's piece of batch b into buffer bf.  A weight lane
+  // writes its axis row at block coordinates: cell f of the block is weight
+  // f + sh of the support, sh the offset of the block start against the
+  // first node.  The z lanes (lanes 0-31 of the set's second wave) also
+  // combine the planes their supports touch into the batch's plane mask.
   auto stage = [&](int bf, int b) {
+    unsigned planes = 0;
     if (kind == 0) {
-      const float v[4] = {fv.x, fv.y, fv.z, fv.w};
+      const unsigned bits = __float_as_uint(fr[W]);
+      const int l0 = (int)((bits >> (10 * pc)) & 1023u);
+      const int sh = win_shift(o_ax, l0, nf_ax, W);
+      float *row = &wsh[bf][pc][pe][0];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int i = 4 * pc + u;          // float of the record
-        if (i < 3 * W) {
-          wrow[bf][i / W][pe][kWinPad + i % W] = v[u];
-        } else if (i == 3 * W) {
-          // the first node: row shifts and the planes the support covers
-          const unsigned bits = __float_as_uint(v[u]);
-          const int sx = win_shift(ox, (int)(bits & 1023u), a.nfx, W);
-          const int sy = win_shift(oy, (int)((bits >> 10) & 1023u), a.nfy, W);
-          const int sz = win_shift(oz, (int)((bits >> 20) & 1023u), a.nfz, W);
-          const int lo = max(0, -sz), hi = min(kSB, W - sz);
-          const unsigned mask = (b * kMmaBatch + pe < it.z && hi > lo)
-                                    ? ((1u << hi) - 1u) & ~((1u << lo) - 1u) : 0u;
-          shifts[bf][pe] = (sx + kWinPad) | ((sy + kWinPad) << 8) | ((sz + kWinPad) << 16) |
-                           (int)(mask << 24);
-        }
+      for (int f = 0; f < kSB; ++f) {
+        float v = 0.f;
+#pragma unroll
+        for (int i = 0; i < W; ++i) v = (f + sh == i) ? fr[i] : v;
+        row[f] = v;
       }
+      const int lo = max(0, -sh), hi = min(kSB, W - sh);
+      if (pc == 2 && b * kMmaBatch + pe < it.z && hi > lo)
+        planes = ((1u << hi) - 1u) & ~((1u << lo) - 1u);
     } else if (kind == 1) {
-      vbas[bf][pe][2 * pc] = make_float2(fv.x, fv.y);
-      vbas[bf][pe][2 * pc + 1] = make_float2(fv.z, fv.w);
+      vbas[bf][pe][2 * pc] = make_float2(fr[0], fr[1]);
+      vbas[bf][pe][2 * pc + 1] = make_float2(fr[2], fr[3]);
     } else if (kind == 2) {
-      rsd[bf][pe][2 * pc] = make_float2(fv.x, fv.y);
-      rsd[bf][pe][2 * pc + 1] = make_float2(fv.z, fv.w);
+      rsd[bf][pe][2 * pc] = make_float2(fr[0], fr[1]);
+      rsd[bf][pe][2 * pc + 1] = make_float2(fr[2], fr[3]);
+    }
+    if ((wv & 7) == 1) {
+      unsigned pm = 0;
+#pragma unroll
+      for (int f = 0; f < kSB; ++f) pm |= __ballot((planes >> f) & 1u) != 0 ? 1u << f : 0u;
+      if (lane == 0) pmask[bf] = pm;
     }
   };
   // the value tile c of batch bf (wave c builds it): column n of the tile
@@ -1109,41 +1127,59 @@ __device__ __forceinline__ void spread_pw_body(const SpreadDev &a, int item, int
     fetch(1);
     list(3);
   }
-  __syncthreads();   // rows zeroed
   if (set == 0 && nb > 0) {
     stage(0, 0);
     fetch(2);
     list(4);
   }
   __syncthreads();
-  for (int n = 0; n < nb; ++n) {
+  // Between two barriers a wave runs the products of batch n - 1 and builds
+  // the operands of batch n.  The set that stages batch n + 1 does that
+  // first (its loads were issued two batches earlier) and its products
+  // after, while the other waves of each SIMD start with their products:
+  // the matrix cores and the vector ALU then work for different waves at
+  // the same time instead of in turn.
+  uint4 ah[2], al[2];
+  bool act_prev = false;
+  for (int n = 0; n <= nb; ++n) {
     const int bf = n & 1;
-    build_values(bf, bf);
-    // the planes of this batch: each lane ORs its eight entries' masks,
-    // then the four lane groups (entries 0-7, 8-15, 16-23, 24-31) combine
-    int sh[8];
-    unsigned pm = 0;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      sh[e] = shifts[bf][e0 + e];
-      pm |= (unsigned)sh[e] >> 24;
+    // the set of batch n + 1 stages it into the other buffer and loads
+    // batch n + 3 and the list of batch n + 5
+    if (set == ((n + 1) & 1) && n + 1 < nb) {
+      stage(bf ^ 1, n + 1);
+      if (n + 3 < nb) {
+        fetch(n + 3);
+        if (n + 5 < nb) list(n + 5);
+      }
     }
-    pm |= __shfl_xor(pm, 16, 64);
-    pm |= __shfl_xor(pm, 32, 64);
-    const bool active = (pm >> z) & 1u;
-    // this wave's A tiles, into registers (the staged rows of this batch
-    // are overwritten two batches on)
-    uint4 ah[2], al[2];
-    if (active) {
+    if (act_prev) {
+#pragma unroll
+      for (int c = 0; c < NCT; ++c) {
+        const sdn_half8 b_hi = __builtin_bit_cast(sdn_half8, sB[bf ^ 1][c][0][lane]);
+        const sdn_half8 b_lo = __builtin_bit_cast(sdn_half8, sB[bf ^ 1][c][1][lane]);
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          const sdn_half8 a_hi = __builtin_bit_cast(sdn_half8, ah[t]);
+          const sdn_half8 a_lo = __builtin_bit_cast(sdn_half8, al[t]);
+          acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a_hi, b_hi, acc[t][c], 0, 0, 0);
+          acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a_hi, b_lo, acc[t][c], 0, 0, 0);
+          acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a_lo, b_hi, acc[t][c], 0, 0, 0);
+        }
+      }
+    }
+    if (n == nb) break;
+    build_values(bf, bf);
+    act_prev = (pmask[bf] >> z) & 1u;
+    // this wave's A tiles, into registers: A[(y, x), entry] =
+    // wz(z) wy(y) wx(x) from the staged rows of this batch
+    if (act_prev) {
       float a0[8], a1[8];
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const int qe = e0 + e;
-        const float zx = wrow[bf][2][qe][((sh[e] >> 16) & 255) + z] *
-                         wrow[bf][0][qe][(sh[e] & 255) + fx];
-        const int yb = ((sh[e] >> 8) & 255) + fy;
-        a0[e] = zx * wrow[bf][1][qe][yb];
-        a1[e] = zx * wrow[bf][1][qe][yb + 2];
+        const float zx = wsh[bf][2][qe][z] * wsh[bf][0][qe][fx];
+        a0[e] = zx * wsh[bf][1][qe][fy];
+        a1[e] = zx * wsh[bf][1][qe][fy + 2];
       }
       unsigned hi0[4], lo0[4], hi1[4], lo1[4];
 #pragma unroll
@@ -1156,31 +1192,7 @@ __device__ __forceinline__ void spread_pw_body(const SpreadDev &a, int item, int
       ah[1] = make_uint4(hi1[0], hi1[1], hi1[2], hi1[3]);
       al[1] = make_uint4(lo1[0], lo1[1], lo1[2], lo1[3]);
     }
-    // the set of batch n + 1 stages it into the other buffer and loads
-    // batch n + 3 and the list of batch n + 5
-    if (set == ((n + 1) & 1) && n + 1 < nb) {
-      stage(bf ^ 1, n + 1);
-      if (n + 3 < nb) {
-        fetch(n + 3);
-        if (n + 5 < nb) list(n + 5);
-      }
-    }
     __syncthreads();
-    if (active) {
-#pragma unroll
-      for (int c = 0; c < NCT; ++c) {
-        const sdn_half8 b_hi = __builtin_bit_cast(sdn_half8, sB[bf][c][0][lane]);
-        const sdn_half8 b_lo = __builtin_bit_cast(sdn_half8, sB[bf][c][1][lane]);
-#pragma unroll
-        for (int t = 0; t < 2; ++t) {
-          const sdn_half8 a_hi = __builtin_bit_cast(sdn_half8, ah[t]);
-          const sdn_half8 a_lo = __builtin_bit_cast(sdn_half8, al[t]);
-          acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a_hi, b_hi, acc[t][c], 0, 0, 0);
-          acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a_hi, b_lo, acc[t][c], 0, 0, 0);
-          acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a_lo, b_hi, acc[t][c], 0, 0, 0);
-        }
-      }
-    }
   }
   // lane holds rows 4 (lane / 16) + i of its row tiles t, i.e. cells
   // (y, x) = (4 h + 2 t + (lane / 16) / 2, 4 ((lane / 16) & 1) + i), of

@@ -1092,28 +1092,26 @@ __device__ __forceinline__ void spread_pw_body(const SpreadDev &a, int item, int
       if (lane == 0) pmask[bf] = pm;
     }
   };
-  // the value tile c of batch bf (wave c builds it): column n of the tile
-  // is (coil, channel, re/im) = 16 c + n, its 8 entries e0 .. e0 + 7
-  auto build_values = [&](int bf, int vb) {
-    if (wv < NCT) {
-      const int col = 16 * wv + r16;
-      const int gl = col / (2 * K), kk = (col >> 1) - gl * K, ri = col & 1;
-      float v[8];
+  // the value tile c of batch bf: column n of the tile is (coil, channel,
+  // re/im) = 16 c + n, its 8 entries e0 .. e0 + 7
+  auto build_values = [&](int bf, int c) {
+    const int col = 16 * c + r16;
+    const int gl = col / (2 * K), kk = (col >> 1) - gl * K, ri = col & 1;
+    float v[8];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        float x = 0.f;
-        if (gl < G) {
-          const float2 m = cmulc(rsd[vb][e0 + e][gl], vbas[vb][e0 + e][kk]);
-          x = (ri ? m.y : m.x) * s;
-        }
-        v[e] = x;
+    for (int e = 0; e < 8; ++e) {
+      float x = 0.f;
+      if (gl < G) {
+        const float2 m = cmulc(rsd[bf][e0 + e][gl], vbas[bf][e0 + e][kk]);
+        x = (ri ? m.y : m.x) * s;
       }
-      unsigned hi[4], lo[4];
-#pragma unroll
-      for (int e = 0; e < 4; ++e) split2(v[2 * e], v[2 * e + 1], hi[e], lo[e]);
-      sB[bf][wv][0][lane] = make_uint4(hi[0], hi[1], hi[2], hi[3]);
-      sB[bf][wv][1][lane] = make_uint4(lo[0], lo[1], lo[2], lo[3]);
+      v[e] = x;
     }
+    unsigned hi[4], lo[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) split2(v[2 * e], v[2 * e + 1], hi[e], lo[e]);
+    sB[bf][c][0][lane] = make_uint4(hi[0], hi[1], hi[2], hi[3]);
+    sB[bf][c][1][lane] = make_uint4(lo[0], lo[1], lo[2], lo[3]);
   };
 
   // prologue: set 0 stages batch 0 and holds batch 2 and the list of batch
@@ -1136,9 +1134,9 @@ __device__ __forceinline__ void spread_pw_body(const SpreadDev &a, int item, int
   // Between two barriers a wave runs the products of batch n - 1 and builds
   // the operands of batch n.  The set that stages batch n + 1 does that
   // first (its loads were issued two batches earlier) and its products
-  // after, while the other waves of each SIMD start with their products:
-  // the matrix cores and the vector ALU then work for different waves at
-  // the same time instead of in turn.
+  // after, while the other set starts with its products and then builds the
+  // value tiles: the matrix cores and the vector ALU then work for
+  // different waves at the same time instead of in turn.
   uint4 ah[2], al[2];
   bool act_prev = false;
   for (int n = 0; n <= nb; ++n) {
@@ -1168,7 +1166,9 @@ __device__ __forceinline__ void spread_pw_body(const SpreadDev &a, int item, int
       }
     }
     if (n == nb) break;
-    build_values(bf, bf);
+    // the value tiles of batch n: waves 0 .. NCT - 1 of the set that does
+    // not stage in this interval
+    if (set == bf && (wv & 7) < NCT) build_values(bf, wv & 7);
     act_prev = (pmask[bf] >> z) & 1u;
     // this wave's A tiles, into registers: A[(y, x), entry] =
     // wz(z) wy(y) wx(x) from the staged rows of this batch

@@ -933,14 +933,11 @@ constexpr int kPwCols = 96;                   // value columns per workgroup at 
 constexpr int kPwRow = 9;
 
 // Coils of one plane-split workgroup for kernel width W and K channels:
-// 2 K value columns each, at most kPwCols, and few enough that one fetch
-// set (512 lanes) loads a batch: 3 weight rows, ceil(K/2) basis pieces and
-// ceil(G/2) residual pieces per entry.
+// 2 K value columns each, at most kPwCols, and at most 16 (a fetch set then
+// always loads a batch: see the piece layout in the kernel).
 __host__ __device__ constexpr int pw_coils(int W, int K) {
   static_cast<void>(W);   // the weight rows take three pieces whatever the width
-  const int by_cols = kPwCols / (2 * K);
-  const int by_fetch = 2 * (512 / kMmaBatch - 3 - (K + 1) / 2);
-  const int g = by_cols < by_fetch ? by_cols : by_fetch;
+  const int g = kPwCols / (2 * K);
   return g < 16 ? g : 16;
 }
 
@@ -956,7 +953,13 @@ __device__ __forceinline__ void spread_pw_body(const SpreadDev &a, int item, int
   constexpr int GMAX = pw_coils(W, K);        // coils of a full workgroup
   constexpr int NVP = (K + 1) / 2;            // basis pieces per entry
   constexpr int NRP = (GMAX + 1) / 2;         // residual pieces per entry
-  static_assert(kMmaBatch * (3 + NVP + NRP) <= 512, "one fetch set loads a batch");
+  // pieces of a fetch set: weight rows in lanes 0-95 (waves 0-1), basis
+  // pieces from lane 128, residual pieces from the next whole wave, so
+  // that no wave mixes piece kinds (a wave that ran two kinds' loads in
+  // turn would wait for the first kind's loads before issuing the second)
+  constexpr int kQv = 4 * kMmaBatch;
+  constexpr int kQr = kQv + (kMmaBatch * NVP + 63) / 64 * 64;
+  static_assert(kQr + kMmaBatch * NRP <= 512, "one fetch set loads a batch");
   static_assert(W <= kSB, "a weight row covers the block");
   // double-buffered staging: batch n is staged into buffer n & 1 one
   // barrier interval ahead; its value tiles are built into buffer n & 1 and
@@ -999,10 +1002,10 @@ __device__ __forceinline__ void spread_pw_body(const SpreadDev &a, int item, int
   int kind, pe, pc;
   if (q < 3 * kMmaBatch) {
     kind = 0; pe = q & (kMmaBatch - 1); pc = q / kMmaBatch;
-  } else if (q < kMmaBatch * (3 + NVP)) {
-    kind = 1; pe = (q - 3 * kMmaBatch) / NVP; pc = q - 3 * kMmaBatch - pe * NVP;
-  } else if (q < kMmaBatch * (3 + NVP + NRP)) {
-    kind = 2; pe = (q - kMmaBatch * (3 + NVP)) / NRP; pc = q - kMmaBatch * (3 + NVP) - pe * NRP;
+  } else if (q >= kQv && q < kQv + kMmaBatch * NVP) {
+    kind = 1; pe = (q - kQv) / NVP; pc = q - kQv - pe * NVP;
+  } else if (q >= kQr && q < kQr + kMmaBatch * NRP) {
+    kind = 2; pe = (q - kQr) / NRP; pc = q - kQr - pe * NRP;
   } else {
     kind = 3; pe = 0; pc = 0;
   }
@@ -1015,11 +1018,8 @@ __device__ __forceinline__ void spread_pw_body(const SpreadDev &a, int item, int
   auto list = [&](int b) {
     const int e = b * kMmaBatch + pe;
     if (kind == 3 || e >= it.z) return;
-    const int raw = a.vlist[it.y + e];
-    // a complemented entry is a support that starts in an earlier block (z
-    // offset below 0); on grids of at least 16 cells per axis no support
-    // meets a block twice, so it is an ordinary entry here
-    L.j = raw < 0 ? ~raw : raw;
+    // kept as loaded: decoding it here would wait for the load at once
+    L.j = a.vlist[it.y + e];
     if (kind != 0) L.id = a.vinfo[it.y + e];
   };
   // this lane's piece of batch b (zeros past the list's end)
@@ -1027,31 +1027,42 @@ __device__ __forceinline__ void spread_pw_body(const SpreadDev &a, int item, int
 #pragma unroll
     for (int i = 0; i <= W; ++i) fr[i] = 0.f;
     if (kind == 3 || b * kMmaBatch + pe >= it.z) return;
+    // a complemented entry is a support that starts in an earlier block (z
+    // offset below 0); on grids of at least 16 cells per axis no support
+    // meets a block twice, so it is an ordinary entry here
+    const int j = L.j < 0 ? ~L.j : L.j;
+    // the lane's piece index, opaque to the compiler: otherwise it keeps a
+    // 64-bit address per piece kind live across the whole loop (and spills
+    // them, and a spill reload waits for every load in flight)
+    int pco = pc;
+    asm volatile("" : "+v"(pco));
     if (kind == 0) {
-      const float *r = a.wts + (size_t)L.j * wrec_stride(W);
-      const float2 *r2 = reinterpret_cast<const float2 *>(r + pc * W);
+      const size_t r = (size_t)j * wrec_stride(W);
+      const float2 *r2 = reinterpret_cast<const float2 *>(a.wts + (r + pco * W));
 #pragma unroll
       for (int i = 0; i < W / 2; ++i) {
         const float2 v = r2[i];
         fr[2 * i] = v.x;
         fr[2 * i + 1] = v.y;
       }
-      fr[W] = r[3 * W];
+      fr[W] = a.wts[r + 3 * W];
     } else if (kind == 1) {
-      const int k = 2 * pc;
-      const float2 v0 = a.V[(size_t)L.id.x * K + k];
-      const float2 v1 = k + 1 < K ? a.V[(size_t)L.id.x * K + k + 1] : make_float2(0.f, 0.f);
+      const int k = 2 * pco;
+      const float2 *vp = a.V + ((size_t)L.id.x * K + k);
+      const float2 v0 = vp[0];
+      const float2 v1 = k + 1 < K ? vp[1] : make_float2(0.f, 0.f);
       fr[0] = v0.x; fr[1] = v0.y; fr[2] = v1.x; fr[3] = v1.y;
     } else {
-      const int c = 2 * pc;
+      const int c = 2 * pco;
       float2 r0 = make_float2(0.f, 0.f), r1 = make_float2(0.f, 0.f);
       if (a.src_plan) {
-        const float2 *sp = a.src + (size_t)L.j * a.groups + g0 + c;
+        const float2 *sp = a.src + ((size_t)j * a.groups + g0 + c);
         if (c < G) r0 = sp[0];
         if (c + 1 < G) r1 = sp[1];
       } else {
-        if (c < G) r0 = a.src[(size_t)(g0 + c) * a.M + L.id.y];
-        if (c + 1 < G) r1 = a.src[(size_t)(g0 + c + 1) * a.M + L.id.y];
+        const float2 *sp = a.src + ((size_t)(g0 + c) * a.M + L.id.y);
+        if (c < G) r0 = sp[0];
+        if (c + 1 < G) r1 = sp[a.M];
       }
       fr[0] = r0.x; fr[1] = r0.y; fr[2] = r1.x; fr[3] = r1.y;
     }

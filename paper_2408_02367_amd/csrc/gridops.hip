@@ -617,11 +617,9 @@ struct MmaFetch {
 __device__ __forceinline__ void mma_list(const SpreadDev &a, const int4 &it, int e, bool all_lanes,
                                          int lane, MmaList &L) {
   L.ok = e < it.z;
-  const int raw = L.ok ? a.vlist[it.y + e] : 0;
-  // a complemented entry is a support that starts in an earlier block (z
-  // offset below 0); on grids of at least 16 cells per axis no support
-  // meets a block twice, so it is an ordinary entry here
-  L.j = raw < 0 ? ~raw : raw;
+  // kept as loaded (decoded where it is used): decoding it here would wait
+  // for this load, and with it for the point loads issued just before
+  L.j = L.ok ? a.vlist[it.y + e] : 0;
   L.id = (L.ok && (all_lanes || lane < kMmaBatch)) ? a.vinfo[it.y + e] : make_int2(0, 0);
 }
 
@@ -630,12 +628,16 @@ __device__ __forceinline__ void mma_fetch(const SpreadDev &a, const MmaList &L, 
                                           bool v_wave, bool r_wave, int g0, int wv, int lane,
                                           MmaFetch<W, MIX, K> &f) {
   const bool ok = L.ok;
+  // a complemented entry is a support that starts in an earlier block (z
+  // offset below 0); on grids of at least 16 cells per axis no support
+  // meets a block twice, so it is an ordinary entry here
+  const int j = L.j < 0 ? ~L.j : L.j;
   if (wv == 0) {
     // one half of the point's record per lane, 16-byte loads: lanes 0..31
     // the x and y weights, lanes 32..63 the z weights and the first node
     static_assert((2 * W) % 4 == 0, "record halves are whole float4s");
     const float4 *wl = reinterpret_cast<const float4 *>(
-        a.wts + (size_t)L.j * wrec_stride(W) + (lane < kMmaBatch ? 0 : 2 * W));
+        a.wts + (size_t)j * wrec_stride(W) + (lane < kMmaBatch ? 0 : 2 * W));
 #pragma unroll
     for (int i = 0; i < W / 2; ++i) {
       const float4 v = ok ? wl[i] : make_float4(0.f, 0.f, 0.f, 0.f);
@@ -658,7 +660,7 @@ __device__ __forceinline__ void mma_fetch(const SpreadDev &a, const MmaList &L, 
         const int g = g0 + c;
         const bool rok = ok && c < NG && g < a.groups;
         f.r[i] = !rok ? make_float2(0.f, 0.f)
-                      : a.src_plan ? a.src[(size_t)L.j * a.groups + g]
+                      : a.src_plan ? a.src[(size_t)j * a.groups + g]
                                    : a.src[(size_t)g * a.M + L.id.y];
       }
     }

@@ -67,20 +67,26 @@ struct Fused {
 
 // Work order over the 8 XCDs.  The hardware deals the workgroups of a
 // launch out to the XCDs round-robin (workgroup L to XCD L % 8), and each
-// XCD has its own L2.  The groups (coils or coil groups) of one work item
-// read the same point records, so they go to one XCD one after another:
-// XCD j runs items j, j + 8, j + 16, ... (the plan's item order, heaviest
-// first, is kept across the XCDs), each for all groups in turn.  The grid
-// holds xcd_grid(items, groups) workgroups; those past the last item exit.
+// XCD has its own L2.  The items are dealt out in chunks of `chunk`
+// consecutive items: XCD j runs chunks j, j + 8, j + 16, ..., and within a
+// chunk each item for all its groups (coils or coil groups) in turn, so the
+// groups of an item, which read the same point records, and neighbouring
+// items of a chunk, which read overlapping grid cells when the items are in
+// spatial order, run close together on one XCD.  The grid holds
+// xcd_grid(items, groups, chunk) workgroups; those past the last item exit.
 constexpr int kXcds = 8;
-inline unsigned xcd_grid(int64_t items, int groups) {
-  return (unsigned)((items + kXcds - 1) / kXcds * kXcds * groups);
+inline unsigned xcd_grid(int64_t items, int groups, int chunk = 1) {
+  const int64_t chunks = (items + chunk - 1) / chunk;
+  return (unsigned)((chunks + kXcds - 1) / kXcds * kXcds * chunk * groups);
 }
-__device__ __forceinline__ bool xcd_item(int items, int groups, int &item, int &group) {
+__device__ __forceinline__ bool xcd_item(int items, int groups, int &item, int &group,
+                                         int chunk = 1) {
   const int j = (int)blockIdx.x % kXcds, r = (int)blockIdx.x / kXcds;
-  const int q = r / groups;
-  item = q * kXcds + j;
-  group = r - q * groups;
+  const int per = chunk * groups;             // workgroups of one chunk
+  const int q = r / per, rr = r - q * per;
+  const int g = rr / groups;
+  item = (q * kXcds + j) * chunk + g;
+  group = rr - g * groups;
   return item < items;
 }
 
@@ -88,8 +94,8 @@ __device__ __forceinline__ bool xcd_item(int items, int groups, int &item, int &
 // over all volumes: start[] are item offsets); -1 past the last item.
 template <typename Dev>
 __device__ __forceinline__ int fused_volume(const Fused<Dev> &f, int groups, int &item,
-                                            int &group) {
-  if (!xcd_item(f.start[f.n], groups, item, group)) return -1;
+                                            int &group, int chunk = 1) {
+  if (!xcd_item(f.start[f.n], groups, item, group, chunk)) return -1;
   int v = 0;
   while (v + 1 < f.n && item >= f.start[v + 1]) ++v;
   item -= f.start[v];
@@ -118,6 +124,7 @@ struct InterpDev {
   unsigned *rmax;
   int nitems;          // work items of this plan (the loss partials' row length)
   int groups;          // output rows per point: coils (mix) or channel groups
+  int chunk;           // items per XCD chunk (the items are in tile order)
 };
 
 constexpr int kThreads = 256;
@@ -315,14 +322,14 @@ __device__ __forceinline__ void interp_body(const InterpDev &a, int item, int gr
 template <int W, bool MIX, bool DC, bool BUF>
 __global__ void __launch_bounds__(kIThreads) k_interp(InterpDev a) {
   int item, grp;
-  if (!xcd_item(a.nitems, a.groups, item, grp)) return;
+  if (!xcd_item(a.nitems, a.groups, item, grp, a.chunk)) return;
   interp_body<W, MIX, DC, BUF>(a, item, grp);
 }
 
 template <int W, bool MIX, bool DC, bool BUF>
 __global__ void __launch_bounds__(kIThreads) k_interp_fused(Fused<InterpDev> f) {
   int item, grp;
-  const int v = fused_volume(f, f.dev[0].groups, item, grp);
+  const int v = fused_volume(f, f.dev[0].groups, item, grp, f.dev[0].chunk);
   if (v < 0) return;
   interp_body<W, MIX, DC, BUF>(f.dev[v], item, grp);
 }
@@ -1441,6 +1448,7 @@ InterpDev interp_dev(const sdn_plan_s &p, const InterpArgs &a) {
   d.rmax = a.dc ? a.rmax : nullptr;
   d.nitems = (int)p.nwork;
   d.groups = a.groups;
+  d.chunk = std::max(1, p.ax[0].ntile);   // about one row of tiles along x
   return d;
 }
 
@@ -1467,7 +1475,7 @@ hipError_t launch_interp(const sdn_plan_s &p, const InterpArgs &a, hipStream_t s
   const bool dc = a.dc != 0;
   const size_t lds = interp_lds_bytes(p);
   if (d.rmax) hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, d.rmax, 1);
-  dim3 grd(xcd_grid(p.nwork, a.groups));
+  dim3 grd(xcd_grid(p.nwork, a.groups, d.chunk));
   hipError_t e;
   switch (p.W) {
     case 4: e = interp_launch<4>(d, nullptr, d.rec_bytes != 0, mix, dc, grd, lds, st); break;
@@ -1501,7 +1509,7 @@ hipError_t launch_interp_fused(const sdn_plan_s *const *plans, const InterpArgs 
     if (f.dev[v].rmax) hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, f.dev[v].rmax, 1);
   }
   f.start[n] = total;
-  dim3 grd(xcd_grid(total, args[0].groups));
+  dim3 grd(xcd_grid(total, args[0].groups, f.dev[0].chunk));
   hipError_t e;
   switch (plans[0]->W) {
     case 4: e = interp_launch<4>(f.dev[0], &f, buf, mix, dc, grd, lds, st); break;

@@ -600,9 +600,9 @@ sdn_status sdn_plan_create(sdn_plan *out, const int64_t shape[3], const float *t
           items.push_back(make_int4(b, (int)acc + st0, std::min(cap, c - st0), 0));
         acc += c;
       }
-      // crowded tiles first: they finish last otherwise
-      std::stable_sort(items.begin(), items.end(),
-                       [](const int4 &a, const int4 &b) { return a.z > b.z; });
+      // items stay in tile order (x fastest): the interpolation deals them
+      // out to the XCDs in runs of neighbouring tiles, whose staged tiles
+      // overlap, so the overlap is read through a shared L2
       p->nwork = (int64_t)items.size();
       s = dalloc(&p->work, items.size(), "plan work list");
       if (s == SDN_OK && !items.empty())

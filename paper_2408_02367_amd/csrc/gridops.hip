@@ -1217,29 +1217,37 @@ __device__ __forceinline__ void spread_pw_body(const SpreadDev &a, int item, int
   // lane holds rows 4 (lane / 16) + i of its row tiles t, i.e. cells
   // (y, x) = (4 h + 2 t + (lane / 16) / 2, 4 ((lane / 16) & 1) + i), of
   // column 16 c + lane % 16 = (coil, channel, re/im)
+  // The partner lane (lane ^ 1) holds the other component of the same
+  // cells: after one exchange, lane re/im = 0 holds (re, im) of cells x0
+  // and x0 + 1, lane re/im = 1 those of x0 + 2 and x0 + 3, so each lane
+  // writes 16 bytes and a store instruction writes whole 64-byte rows of
+  // 8 cells (single 4-byte stores of interleaved components, half the
+  // lanes per cell, took about 40% of the kernel's time).
   const float inv = 1.f / s;
   const int qq = lane >> 4;
-  const int x0 = 4 * (qq & 1);
+  const int ri = lane & 1;
+  const int xc = 4 * (qq & 1) + 2 * ri;   // the first of this lane's two cells
 #pragma unroll
   for (int c = 0; c < NCT; ++c) {
     const int col = 16 * c + r16;
-    const int gl = col / (2 * K), kk = (col >> 1) - gl * K, ri = col & 1;
-    if (gl >= G) continue;
-    const int g = g0 + gl;
+    const int gl = col / (2 * K), kk = (col >> 1) - gl * K;
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
+      const float v0 = acc[t][c][0] * inv, v1 = acc[t][c][1] * inv;
+      const float v2 = acc[t][c][2] * inv, v3 = acc[t][c][3] * inv;
+      const float p0 = __shfl_xor(ri ? v0 : v2, 1, 64);
+      const float p1 = __shfl_xor(ri ? v1 : v3, 1, 64);
+      const float4 out = ri ? make_float4(p0, v2, p1, v3) : make_float4(v0, p0, v1, p1);
+      if (gl >= G) continue;
+      const int g = g0 + gl;
       const int y = 4 * h + 2 * t + (qq >> 1);
       if (it.w >= 0) {
-        float *pp = reinterpret_cast<float *>(
-            a.part + (((size_t)it.w * a.groups + g) * K + kk) * kSBCells + z * 64 + y * 8 + x0);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) pp[2 * i + ri] = acc[t][c][i] * inv;
-      } else if (oz + z < a.nfz && oy + y < a.nfy) {
-        float *gp = reinterpret_cast<float *>(
-            a.grid + (size_t)(g * K + kk) * a.G + ((size_t)(oz + z) * a.nfy + oy + y) * a.nfx + ox + x0);
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-          if (ox + x0 + i < a.nfx) gp[2 * i + ri] = acc[t][c][i] * inv;
+        *reinterpret_cast<float4 *>(
+            a.part + (((size_t)it.w * a.groups + g) * K + kk) * kSBCells + z * 64 + y * 8 + xc) = out;
+      } else if (oz + z < a.nfz && oy + y < a.nfy && ox + xc < a.nfx) {
+        // fine sizes are even, so both cells of the pair lie inside
+        *reinterpret_cast<float4 *>(a.grid + (size_t)(g * K + kk) * a.G +
+                                    ((size_t)(oz + z) * a.nfy + oy + y) * a.nfx + ox + xc) = out;
       }
     }
   }

@@ -860,36 +860,33 @@ __device__ __forceinline__ void spread_mma_body(const SpreadDev &a, int item, in
     }
   }
   if (!coil_ok) return;
-  // lane holds rows (y,x) = 16t + 4(lane/16) + i, column (re/im, z) = lane % 16
+  // lane holds rows (y,x) = 16t + 4(lane/16) + i, column (re/im, z) =
+  // lane % 16.  Lane ^ 8 holds the other component of the same cells:
+  // after one exchange, lane re/im = 0 holds (re, im) of cells x0 and
+  // x0 + 1 of its row, lane re/im = 1 those of x0 + 2 and x0 + 3, so each
+  // lane writes 16 bytes and a store writes whole 64-byte rows of 8 cells.
   const float inv = 1.f / s;
-  const int ri = (lane >> 3) & 1, z = lane & 7;
-  if (it.w >= 0) {
-    float *pp = reinterpret_cast<float *>(a.part + ((size_t)it.w * a.groups + grp) * K * kSBCells);
+  const int ri = (lane >> 3) & 1, z = lane & 7, qq = lane >> 4;
+  const int xc = 4 * (qq & 1) + 2 * ri;   // the first of this lane's two cells
 #pragma unroll
-    for (int k = 0; k < K; ++k)
+  for (int k = 0; k < K; ++k)
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int row = 16 * t + 4 * (lane >> 4) + i;
-          pp[((size_t)k * kSBCells + z * 64 + row) * 2 + ri] = acc[t][k][i] * inv;
-        }
-    return;
-  }
-  if (oz + z >= a.nfz) return;
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    float *gp = reinterpret_cast<float *>(a.grid + (size_t)(grp * K + k) * a.G);
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int row = 16 * t + 4 * (lane >> 4) + i;
-        const int gx = ox + (row & 7), gy = oy + (row >> 3);
-        if (gx < a.nfx && gy < a.nfy)
-          gp[(((size_t)(oz + z) * a.nfy + gy) * a.nfx + gx) * 2 + ri] = acc[t][k][i] * inv;
+    for (int t = 0; t < 4; ++t) {
+      const float v0 = acc[t][k][0] * inv, v1 = acc[t][k][1] * inv;
+      const float v2 = acc[t][k][2] * inv, v3 = acc[t][k][3] * inv;
+      const float p0 = __shfl_xor(ri ? v0 : v2, 8, 64);
+      const float p1 = __shfl_xor(ri ? v1 : v3, 8, 64);
+      const float4 out = ri ? make_float4(p0, v2, p1, v3) : make_float4(v0, p0, v1, p1);
+      const int y = 2 * t + (qq >> 1);
+      if (it.w >= 0) {
+        *reinterpret_cast<float4 *>(a.part + (((size_t)it.w * a.groups + grp) * K + k) * kSBCells +
+                                    z * 64 + y * 8 + xc) = out;
+      } else if (oz + z < a.nfz && oy + y < a.nfy && ox + xc < a.nfx) {
+        // fine sizes are even, so both cells of the pair lie inside
+        *reinterpret_cast<float4 *>(a.grid + (size_t)(grp * K + k) * a.G +
+                                    ((size_t)(oz + z) * a.nfy + oy + y) * a.nfx + ox + xc) = out;
       }
-  }
+    }
 }
 
 template <int W, bool MIX, int K, int NG>

@@ -100,3 +100,15 @@ def test_plane_split_engine(K, B):
     _check_grad_and_adjoint(c, p)
     if K * B >= 32:
         assert _plan(c).spread_engine(B, K) == "planes"
+
+
+@pytest.mark.parametrize("engine", ["planes", "matrix"])
+def test_matrix_engines_ragged_blocks(engine):
+    """Both matrix-core engines on fine grids that 8-cell blocks do not
+    divide on any axis (36 x 42 x 50 cells: the last block of each axis is
+    cut), so their write-out of cell pairs meets every edge, against the
+    oracle."""
+    c = _case(5, 4, shape=(18, 21, 25), C=6, T=7, seed=61)
+    p = _plan(c, spread_engine=engine)
+    assert p.spread_engine(4, 5) == engine
+    _check_grad_and_adjoint(c, p)

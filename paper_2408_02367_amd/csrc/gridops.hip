@@ -705,7 +705,8 @@ __device__ __forceinline__ void spread_mma_body(const SpreadDev &a, int item, in
   const int rem = it.x - bzi * (a.nbx * a.nby);
   const int byi = rem / a.nbx, bxi = rem - byi * a.nbx;
   const int ox = bxi * kSB, oy = byi * kSB, oz = bzi * kSB;
-  const float s = value_scale(absmax, MIX);
+  // an empty block only writes zeros: no need to wait for the scale
+  const float s = it.z > 0 ? value_scale(absmax, MIX) : 1.f;
 
   // zero the weight rows once; each batch rewrites only the W weights
   for (int i = tid; i < 2 * 3 * kMmaBatch * kWinLen; i += 64 * NG) (&wrow[0][0][0][0])[i] = 0.f;
@@ -922,14 +923,16 @@ __global__ void __launch_bounds__(64 * NG) k_spread_mma_fused(Fused<SpreadDev> f
 // its 16-column tiles is built once per batch (by one wave) into LDS; the
 // sixteen waves of the workgroup split the 32 (plane, y-pair) row tiles,
 // wave w taking two y pairs of plane w / 2, and build their A tiles
-// themselves.  A block's list is sorted by the z offset of the points, so
-// the supports of one batch cover few planes: a wave whose plane no entry
-// of the batch touches skips the batch (its operand build and products).
-// The entries' data are loaded by two alternating sets of eight waves (one
-// 16-byte piece per lane: a piece of a weight record, two basis values or
-// two residuals), two batches ahead of their use, and their list entries
-// two batches ahead of that.  Used when every fine axis is at least 16
-// cells, so that no kernel support can touch both ends of a block.
+// themselves from weight rows staged at the block's own coordinates.  A
+// block's list is sorted by the z offset of the points, so the supports of
+// one batch cover few planes: a wave whose plane no entry of the batch
+// touches skips the batch (its operand build and products).  The entries'
+// data are loaded by two alternating sets of eight waves (one piece per
+// lane: the weights of one axis with the packed first node, two basis
+// values or two residuals), two batches ahead of their use, and their list
+// entries two batches ahead of that.  Used when every fine axis is at
+// least 16 cells, so that no kernel support can touch both ends of a
+// block.
 constexpr int kPwWaves = 16;                  // waves of a plane-split workgroup
 constexpr int kPwCols = 96;                   // value columns per workgroup at most
 // A staged weight row holds the 8 weights of one axis at the block's own
@@ -985,7 +988,8 @@ __device__ __forceinline__ void spread_pw_body(const SpreadDev &a, int item, int
   const int rem = it.x - bzi * (a.nbx * a.nby);
   const int byi = rem / a.nbx, bxi = rem - byi * a.nbx;
   const int ox = bxi * kSB, oy = byi * kSB, oz = bzi * kSB;
-  const float s = value_scale(absmax, true);
+  // an empty block only writes zeros: no need to wait for the scale
+  const float s = it.z > 0 ? value_scale(absmax, true) : 1.f;
   const int nb = (it.z + kMmaBatch - 1) / kMmaBatch;
 
   // this wave's row tiles: y pairs 2 h and 2 h + 1 of plane z

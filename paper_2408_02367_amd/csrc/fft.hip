@@ -438,7 +438,10 @@ k_ifftx_post_ct(PostArgs a) {
   const LineGeom &g = a.g;
   const int tid = threadIdx.x;
   const int B = a.B, R = C / B;
-  const int y0 = blockIdx.x * R, z = blockIdx.y, k = blockIdx.z;
+  // channels fastest: the K workgroups of one image row run together and
+  // read its coil maps while they are in the caches
+  const int k = (int)blockIdx.x % a.K;
+  const int y0 = (int)blockIdx.x / a.K * R, z = blockIdx.y;
   const size_t zf = fine_pos(z, g.hz, g.nfz);
   if (tid < C) {
     const int r = tid / B, b = tid - r * B;
@@ -602,7 +605,7 @@ hipError_t launch_post_ifftx(const sdn_plan_s &p, const float2 *grid, int K,
   if (fft_len_ct(L) && B <= 16 && 16 % B == 0 && a.g.Nz <= 65535 && K <= 65535) {
     const bool c8 = 8 % B == 0;
     const int R = (c8 ? 8 : 16) / B;
-    dim3 grd((unsigned)((a.g.Ny + R - 1) / R), (unsigned)a.g.Nz, (unsigned)K);
+    dim3 grd((unsigned)((a.g.Ny + R - 1) / R * K), (unsigned)a.g.Nz);
 #define SDN_POST_CT(LEN)                                                                    \
   case LEN:                                                                                 \
     if (c8) hipLaunchKernelGGL((k_ifftx_post_ct<LEN, 8>), grd, dim3(kPostThreads), 0, st, a); \

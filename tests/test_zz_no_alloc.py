@@ -64,6 +64,21 @@ def test_two_calls_in_a_row_equal_the_allocating_entry_point():
         assert torch.equal(loss, l_ref) and torch.equal(grad, g_ref), shape
 
 
+def test_plane_split_spreading_without_allocation():
+    # 8 coils x 6 channels: the plane-split matrix-core spreading; then a
+    # smaller call with the one-wave-per-coil engine
+    cases = [((16, 16, 16), 6, 10, 8, 9, 2, 300, 75), ((16, 14, 18), 4, 5, 3, 6, 3, 400, 76)]
+    for (shape, K, C, B, T, L, S, seed), engine in zip(cases, ("planes", "matrix")):
+        p, x, s, V, ci, d = _case(shape, K, C, B, T, L, S, seed)
+        assert p.spread_engine(B, K) == engine
+        assert p.workspace_size(B, K) < LIMIT
+        st, loss, grad = _noalloc(p, x, s, ci, V, d)
+        assert st == 0, sdn.lib().sdn_last_error().decode()
+        l_ref, g_ref = sdn.mrf_dc_grad(p, x, s, ci, V, d)
+        torch.cuda.synchronize()
+        assert torch.equal(loss, l_ref) and torch.equal(grad, g_ref), shape
+
+
 def test_coil_passes_when_the_static_array_is_too_small_for_all_coils():
     # 80^3 fine grids: 4 MiB per channel, 5 channels per coil, 4 coils do not fit
     p, x, s, V, ci, d = _case((40, 40, 40), 5, 6, 4, 6, 8, 800, 73)
